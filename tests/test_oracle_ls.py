@@ -1,0 +1,153 @@
+"""Pins of the oracle's Lippmann-Schwinger data term.
+
+* BiCGSTAB agrees with a dense LU solve of I - G diag(x) built column by
+  column from the operator (8^3, 12^3);
+* first-Born limit: (u(eps x) - u_in)/eps -> G(x u_in) with error O(eps);
+* at x = 0 the LS gradient is exactly the first-Born gradient;
+* adjoint identity <J v, w> = <v, J^H w>, with J v from an independent
+  tangent solve;
+* the gradient matches FP64 central finite differences of the loss on 16^3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import green, lsmodel
+
+LAM0, NB = syn.LAMBDA0_UM, syn.N_B
+
+
+def _geom(N):
+    return lsmodel.Geometry(N=N, h=LAM0 / 4, lambda0=LAM0, n_b=NB)
+
+
+def _phantom(N, seed):
+    rng = np.random.default_rng(seed)
+    dn = syn.phantom_ellipsoids(N, LAM0 / 4, rng, n_incl=3, dn_range=(0.01, 0.05))
+    return syn.scattering_potential(dn)
+
+
+def _dense_operator(model, x):
+    N = model.geom.N
+    n = N ** 3
+    A = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[:] = 0
+        e[j] = 1
+        col = e.reshape(N, N, N)
+        A[:, j] = (col - model.G(x * col)).ravel()
+    return A
+
+
+@pytest.mark.parametrize("N", [8, 12])
+def test_bicgstab_matches_dense_lu(N):
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    x = _phantom(N, 100 + N) + 5.0
+    d = syn.illumination_directions(1, 35.0, np.random.default_rng(N))[0]
+    uin = lsmodel.incident_field(geom, d)
+    u, it, st, _ = model.solve_forward(x, uin, 1e-14, 500)
+    assert st == lsmodel.CONVERGED and it > 2
+    A = _dense_operator(model, x)
+    ud = np.linalg.solve(A, uin.ravel()).reshape(u.shape)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-12
+
+
+def test_born_limit_is_first_order():
+    N = 12
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    x = _phantom(N, 5)
+    d = (0.2, -0.1, math.sqrt(1 - 0.05))
+    uin = lsmodel.incident_field(geom, d)
+    born = model.G(x * uin)
+    eps = np.array([1e-1, 1e-2, 1e-3, 1e-4])
+    err = []
+    for e in eps:
+        u, _, st, _ = model.solve_forward(e * x, uin, 1e-15, 500)
+        err.append(np.linalg.norm((u - uin) / e - born) / np.linalg.norm(born))
+    slope = np.polyfit(np.log(eps), np.log(err), 1)[0]
+    assert abs(slope - 1.0) < 0.05, (slope, err)
+
+
+def test_gradient_at_zero_equals_born_gradient():
+    N = 12
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    dirs = syn.illumination_directions(3, 35.0, np.random.default_rng(1))
+    rng = np.random.default_rng(2)
+    y = rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))
+    idx = [0, 1, 2]
+    x0 = np.zeros((N, N, N))
+    g_ls, f_ls, st = model.grad(x0, y, dirs, idx, 1 / 3, 1e-12, 100, model="ls")
+    g_b, f_b, _ = model.grad(x0, y, dirs, idx, 1 / 3, 1e-12, 100, model="born")
+    assert all(s[0] == 0 and s[1] == 0 for s in st)
+    assert np.max(np.abs(g_ls - g_b)) <= 1e-14 * np.max(np.abs(g_b))
+    assert f_ls == pytest.approx(f_b, rel=1e-15)
+    # At x = 0 the prediction is zero, so r_l = -y_l and the gradient is
+    # (1/3) sum_l Re(conj(u_in,l) G^H S^T (-y_l)).
+    ref = np.zeros((N, N, N))
+    for l in idx:
+        uin = lsmodel.incident_field(geom, dirs[l])
+        ref += np.real(np.conj(uin) * green.apply_GH(model.ghat, model.detector_T(-y[l])))
+    assert np.max(np.abs(g_b - ref / 3)) <= 1e-14 * np.max(np.abs(ref))
+    assert f_b == pytest.approx(0.5 / 3 * float(np.sum(np.abs(y) ** 2)), rel=1e-14)
+
+
+def test_adjoint_identity():
+    N = 12
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    x = _phantom(N, 9)
+    d = syn.illumination_directions(1, 35.0, np.random.default_rng(4))[0]
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal((N, N, N))
+    w = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    Jv = model.tangent(x, d, v, 1e-14, 500)
+    JHw = model.vjp(x, d, w, 1e-14, 500)
+    lhs = np.vdot(Jv, w)
+    rhs = np.sum(v * JHw)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-11
+
+
+@pytest.mark.slow
+def test_gradient_matches_central_differences():
+    N = 16
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    xt = _phantom(N, 21)
+    dirs = syn.illumination_directions(2, 35.0, np.random.default_rng(3))
+    idx = [0, 1]
+    yc, _ = model.forward(xt, dirs, idx, 1e-14, 500)
+    y = syn.add_noise(yc, 30.0, np.random.default_rng(4))
+    x = 0.5 * xt
+    scale = 0.5
+    g, f, _ = model.grad(x, y, dirs, idx, scale, 1e-14, 500)
+
+    def loss(xx):
+        H, _ = model.forward(xx, dirs, idx, 1e-14, 500)
+        return scale * 0.5 * float(np.sum(np.abs(H - y) ** 2))
+
+    assert loss(x) == pytest.approx(f, rel=1e-12)
+    # step 1e-4 max(x): smaller steps are limited by the 1e-14 solver
+    # tolerance (loss differences of ~1e-11), larger ones by O(step^2).
+    step = 1e-4 * np.max(x)
+    rng = np.random.default_rng(6)
+    checks = []
+    for _ in range(3):
+        e = rng.standard_normal(x.shape)
+        e /= np.linalg.norm(e)
+        fd = (loss(x + step * e) - loss(x - step * e)) / (2 * step)
+        checks.append((fd, float(np.sum(g * e))))
+    big = np.argsort(-np.abs(g).ravel())[:4]
+    for flat in big:
+        e = np.zeros(x.size)
+        e[flat] = 1.0
+        e = e.reshape(x.shape)
+        fd = (loss(x + step * e) - loss(x - step * e)) / (2 * step)
+        checks.append((fd, float(g.ravel()[flat])))
+    for fd, an in checks:
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.max(np.abs(g))), (fd, an)
