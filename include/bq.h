@@ -1,0 +1,190 @@
+/*
+ * bq -- MI355X (gfx950) hot path of the mini-batch quasi-Newton proximal
+ * method for TV-constrained 3D reconstruction (Hong, Pham, Yavneh, Unser,
+ * arXiv:2307.02043).
+ *
+ * The library evaluates the two kernels that dominate each iteration of
+ * the method's Algorithm 4.1:
+ *
+ *   - the mini-batch data-term gradient  grad F_s(x) = (S/L) sum_{l in S_s}
+ *     grad f_l(x),  f_l(x) = 1/2 ||H_l(x) - y_l||^2  (Section 1 eq.
+ *     defMainPro, Section 4 eq. NewModelPro), where H_l is the optical
+ *     diffraction tomography model of Section 6: the Lippmann-Schwinger
+ *     equation (I - G diag(x)) u_l = u_in,l solved by BiCGSTAB, one solve
+ *     for H_l and two for grad f_l; or its first-Born linearisation;
+ *
+ *   - the weighted proximal mapping of constrained TV (Section 3.4
+ *     definition of the WPM; Section 4.1 dual formulation; Lemma 4.1;
+ *     Theorem 3.1 with the metric tau I + u u^T of Algorithm 4.2).
+ *
+ * Conventions common to all calls
+ *   - Arrays are C-order [z][y][x] with N^3 voxels (x fastest).  Complex
+ *     arrays are interleaved (re, im) pairs: complex64 (2 x float) when the
+ *     context precision is BQ_F32, complex128 (2 x double) for BQ_F64; real
+ *     arrays are float / double accordingly.
+ *   - Pointers named "device" must point to device memory of the current
+ *     HIP device; "host" pointers to host memory.  All arrays are owned by
+ *     the caller: the library never frees them and keeps no reference to
+ *     them after the call returns.
+ *   - Work is enqueued on the stream given at creation; each call
+ *     synchronises that stream before returning (it reads solver status),
+ *     so outputs are ready when it returns.
+ *   - A context is not thread-safe; use one per host thread.
+ *   - Return value: BQ_OK (0), a negative error (no output written or
+ *     outputs undefined), or a positive warning (outputs written; at least
+ *     one solve did not converge cleanly; per-system detail in the stats).
+ *     bq_last_error() describes the last error or warning of a context.
+ *
+ * Physical units: lengths in micrometres; x is the scattering potential
+ * k0^2 (n^2 - n_b^2) in um^-2; the discrete Green's operator includes the
+ * voxel volume, so G is dimensionless.
+ */
+#ifndef BQ_H
+#define BQ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BQ_OK = 0,
+  BQ_EINVAL = -1,        /* invalid argument (null pointer, size, index)   */
+  BQ_ENOMEM = -2,        /* device allocation failed                        */
+  BQ_EDEVICE = -3,       /* HIP runtime error                               */
+  BQ_EUNSUPPORTED = -4,  /* grid size without a kernel instantiation        */
+  BQ_NOTCONV = 1,        /* a solve hit max_iter before reaching tol        */
+  BQ_BREAKDOWN = 2,      /* a BiCGSTAB scalar (rho, <rhat,v>, omega) vanished */
+  BQ_NONFINITE = 3       /* NaN/Inf met in a solve                          */
+} bq_status;
+
+typedef enum { BQ_F32 = 0, BQ_F64 = 1 } bq_precision;
+typedef enum { BQ_MODEL_LS = 0, BQ_MODEL_BORN = 1 } bq_model;
+
+/* flags of bq_geom */
+#define BQ_FLAG_PLAIN 1u /* solve one illumination at a time, with a host
+                            round trip per BiCGSTAB iteration (baseline) */
+
+/* Grid, optics and solver settings (Section 6.1 describes the setting). */
+typedef struct {
+  int N;             /* grid edge; supported: 8 12 16 24 32 48 64 96 128 256 */
+  double h_um;       /* voxel edge (um)                                     */
+  double lambda0_um; /* vacuum wavelength (um)                              */
+  double n_b;        /* background refractive index                         */
+  int precision;     /* bq_precision of fields and FFTs                     */
+  int model;         /* bq_model                                            */
+  double tol;        /* BiCGSTAB relative residual tolerance (>= 0)         */
+  int max_iter;      /* BiCGSTAB iteration cap (>= 0)                       */
+  unsigned flags;    /* BQ_FLAG_*                                           */
+} bq_geom;
+
+/* Unit propagation direction of a plane-wave illumination
+ * u_in(r) = exp(i k_b d . r), k_b = 2 pi n_b / lambda0 (Section 6.1). */
+typedef struct {
+  double dx, dy, dz;
+} bq_illum;
+
+/* Per-illumination outcome of the solves of one call. */
+typedef struct {
+  int iters_fwd, iters_adj;   /* BiCGSTAB iterations (0 for the Born model) */
+  int status_fwd, status_adj; /* 0 converged, 1 not converged, 2 breakdown,
+                                 3 non-finite                               */
+  double relres_fwd, relres_adj; /* final relative recursive residuals      */
+} bq_solve_stats;
+
+typedef struct bq_ctx bq_ctx;
+
+/* Create a context for one geometry and a set of L illuminations.
+ *   g      host, geometry/solver settings (copied)
+ *   dirs   host, L unit directions (copied; |d| must be 1 within 1e-6)
+ *   stream hipStream_t to enqueue on (NULL = default stream)
+ *   out    host, receives the context
+ * Precomputes the Green's transfer function of the padded grid on the
+ * device.  Errors: BQ_EINVAL, BQ_EUNSUPPORTED, BQ_ENOMEM, BQ_EDEVICE. */
+bq_status bq_create(const bq_geom* g, const bq_illum* dirs, int L, void* stream, bq_ctx** out);
+
+/* Release all device memory of a context.  NULL is accepted. */
+bq_status bq_destroy(bq_ctx* ctx);
+
+/* Text of the last error or warning of ctx (or of the last failed
+ * bq_create when ctx is NULL).  Valid until the next call on ctx. */
+const char* bq_last_error(const bq_ctx* ctx);
+
+/* Forward model H_l(x) for the illuminations idx[0..B-1] (Section 6: one
+ * Lippmann-Schwinger solve per illumination; first Born: S G(x u_in)).
+ *   x      device, N^3 real potential
+ *   idx    host, B indices in [0, L)
+ *   y_out  device, B x N x N complex: the scattered field S(u_l - u_in,l) on
+ *          the detector plane z = N-1
+ *   st     host, B entries or NULL */
+bq_status bq_forward(bq_ctx* ctx, const void* x, const int* idx, int B, void* y_out,
+                     bq_solve_stats* st);
+
+/* Total fields u_l = (I - G diag(x))^-1 u_in,l for idx[0..B-1].
+ *   u_out  device, B x N^3 complex (Born model: u_in,l)  */
+bq_status bq_fields(bq_ctx* ctx, const void* x, const int* idx, int B, void* u_out,
+                    bq_solve_stats* st);
+
+/* Mini-batch gradient and loss (Section 4 eq. NewModelPro with the scale
+ * S/L passed explicitly):
+ *   g_out = scale * sum_b Re(conj(u_b) . w_b),
+ *   (I - G^H diag(x)) w_b = G^H S^T r_b,  r_b = S(u_b - u_in,b) - y_b,
+ *   *loss = scale * sum_b 1/2 ||r_b||^2.
+ *   x      device, N^3 real
+ *   y      device, B x N x N complex, y[b] measured for illumination idx[b]
+ *   g_out  device, N^3 real, overwritten
+ *   loss   host, may be NULL
+ *   st     host, B entries or NULL */
+bq_status bq_grad(bq_ctx* ctx, const void* x, const void* y, const int* idx, int B, double scale,
+                  void* g_out, double* loss, bq_solve_stats* st);
+
+/* Apply the discrete Green's operator to B complex fields:
+ * out_b = G v_b (adjoint != 0: G^H v_b).  v, out: device, B x N^3 complex;
+ * v and out must not overlap. */
+bq_status bq_green_apply(bq_ctx* ctx, const void* v, void* out, int B, int adjoint);
+
+/* ---------------------------------------------------------------------
+ * Weighted proximal mapping of constrained TV
+ * --------------------------------------------------------------------- */
+typedef enum { BQ_TV_ISO = 0, BQ_TV_ANISO = 1 } bq_tv;
+typedef enum { BQ_SET_NONE = 0, BQ_SET_NONNEG = 1 } bq_set;
+
+typedef struct {
+  int newton_total;  /* semi-smooth Newton passes over all dual iterations */
+  int newton_max;    /* most passes in one dual iteration                   */
+  double beta_last;  /* root of Theorem 3.1's phi at the output             */
+  double phi_last;   /* |phi(beta_last)|                                    */
+} bq_prox_stats;
+
+typedef struct bq_prox bq_prox;
+
+/* Workspace for proximal mappings of an nz x ny x nx image.
+ * Errors: BQ_EINVAL, BQ_ENOMEM, BQ_EDEVICE. */
+bq_status bq_prox_create(int nz, int ny, int nx, int precision, void* stream, bq_prox** out);
+bq_status bq_prox_destroy(bq_prox* p);
+const char* bq_prox_last_error(const bq_prox* p);
+
+/* x = argmin_{x in C} 1/2 ||x - v||^2_{tau I + u u^T} + lambda TV(x)
+ * (Section 4 eq. SecondProximal_WPMTV, lambda = a_k S lambda of the
+ * outer iteration), by n_iter accelerated projected-gradient iterations on
+ * the dual of Section 4.1 (step tau / (12 lambda), Lemma 4.1 with
+ * omega_min = tau), the projection onto C by Theorem 3.1 with the
+ * semi-smooth Newton root-find of Algorithm 4.3 (safeguarded), and the
+ * Woodbury inverse of the metric (Section 4.3).  Output x(P_K).
+ *   v      device, image (nz*ny*nx real, precision of p)
+ *   tau    > 0
+ *   u      device, rank-one factor of the metric, or NULL for tau I
+ *   lambda > 0
+ *   tv     bq_tv;  cset  bq_set;  n_iter >= 0
+ *   x_out  device, image, overwritten
+ *   P_io   device, 3 x image (component d = finite difference along array
+ *          axis d: 0 = z, 1 = y, 2 = x) or NULL.  When given it is the
+ *          starting dual point and receives P_K; NULL starts from zero.
+ *   st     host or NULL */
+bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* u, double lambda, int tv,
+                   int cset, int n_iter, void* x_out, void* P_io, bq_prox_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BQ_H */

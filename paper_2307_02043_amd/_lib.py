@@ -1,0 +1,79 @@
+"""ctypes declarations of the bq C ABI (include/bq.h).
+
+Loading fails loudly when libbq.so has not been built: there is no CPU
+fallback anywhere in this package.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbq.so")
+
+BQ_OK, BQ_EINVAL, BQ_ENOMEM, BQ_EDEVICE, BQ_EUNSUPPORTED = 0, -1, -2, -3, -4
+BQ_NOTCONV, BQ_BREAKDOWN, BQ_NONFINITE = 1, 2, 3
+BQ_F32, BQ_F64 = 0, 1
+BQ_MODEL_LS, BQ_MODEL_BORN = 0, 1
+BQ_FLAG_PLAIN = 1
+BQ_TV_ISO, BQ_TV_ANISO = 0, 1
+BQ_SET_NONE, BQ_SET_NONNEG = 0, 1
+
+EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
+            "bq_grad", "bq_green_apply", "bq_prox_create", "bq_prox_destroy",
+            "bq_prox_last_error", "bq_wprox")
+
+
+class Geom(ct.Structure):
+    _fields_ = [("N", ct.c_int), ("h_um", ct.c_double), ("lambda0_um", ct.c_double),
+                ("n_b", ct.c_double), ("precision", ct.c_int), ("model", ct.c_int),
+                ("tol", ct.c_double), ("max_iter", ct.c_int), ("flags", ct.c_uint)]
+
+
+class Illum(ct.Structure):
+    _fields_ = [("dx", ct.c_double), ("dy", ct.c_double), ("dz", ct.c_double)]
+
+
+class SolveStats(ct.Structure):
+    _fields_ = [("iters_fwd", ct.c_int), ("iters_adj", ct.c_int),
+                ("status_fwd", ct.c_int), ("status_adj", ct.c_int),
+                ("relres_fwd", ct.c_double), ("relres_adj", ct.c_double)]
+
+
+class ProxStats(ct.Structure):
+    _fields_ = [("newton_total", ct.c_int), ("newton_max", ct.c_int),
+                ("beta_last", ct.c_double), ("phi_last", ct.c_double)]
+
+
+_lib = None
+
+
+def load() -> ct.CDLL:
+    """Load libbq.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ct.CDLL(LIB_PATH)
+    P, I, D = ct.c_void_p, ct.c_int, ct.c_double
+    sig = {
+        "bq_create": ([ct.POINTER(Geom), ct.POINTER(Illum), I, P, ct.POINTER(P)], I),
+        "bq_destroy": ([P], I),
+        "bq_last_error": ([P], ct.c_char_p),
+        "bq_forward": ([P, P, ct.POINTER(I), I, P, ct.POINTER(SolveStats)], I),
+        "bq_fields": ([P, P, ct.POINTER(I), I, P, ct.POINTER(SolveStats)], I),
+        "bq_grad": ([P, P, P, ct.POINTER(I), I, D, P, ct.POINTER(D), ct.POINTER(SolveStats)], I),
+        "bq_green_apply": ([P, P, P, I, I], I),
+        "bq_prox_create": ([I, I, I, I, P, ct.POINTER(P)], I),
+        "bq_prox_destroy": ([P], I),
+        "bq_prox_last_error": ([P], ct.c_char_p),
+        "bq_wprox": ([P, P, D, P, D, I, I, I, P, P, ct.POINTER(ProxStats)], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib

@@ -1,0 +1,213 @@
+"""Python binding of the bq library: argument marshalling only.
+
+Every step of the data-term gradient and of the weighted prox runs in the
+HIP kernels of libbq.so; torch is used for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class BQError(RuntimeError):
+    """A negative status from the library."""
+
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bq status {status}: {msg}")
+        self.status = status
+
+
+@dataclass
+class SolveInfo:
+    status: int                 # library return value (0 or a positive warning)
+    iters_fwd: list
+    iters_adj: list
+    status_fwd: list
+    status_adj: list
+    relres_fwd: list
+    relres_adj: list
+
+
+def _stats(arr, B, status) -> SolveInfo:
+    return SolveInfo(status, [arr[i].iters_fwd for i in range(B)],
+                     [arr[i].iters_adj for i in range(B)],
+                     [arr[i].status_fwd for i in range(B)],
+                     [arr[i].status_adj for i in range(B)],
+                     [arr[i].relres_fwd for i in range(B)],
+                     [arr[i].relres_adj for i in range(B)])
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+class LSContext:
+    """Green's operator, Lippmann-Schwinger solves and the mini-batch
+    gradient for one grid and a set of illumination directions."""
+
+    def __init__(self, N: int, h_um: float, lambda0_um: float, n_b: float,
+                 directions, precision: str = "f32", model: str = "ls",
+                 tol: float = 1e-5, max_iter: int = 300, plain: bool = False,
+                 stream: torch.cuda.Stream | None = None):
+        self._lib = L.load()
+        self.N = int(N)
+        self.precision = precision
+        self.rdtype = torch.float32 if precision == "f32" else torch.float64
+        self.cdtype = torch.complex64 if precision == "f32" else torch.complex128
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        d = np.ascontiguousarray(np.asarray(directions, dtype=np.float64).reshape(-1, 3))
+        self.L = d.shape[0]
+        g = L.Geom(self.N, float(h_um), float(lambda0_um), float(n_b),
+                   L.BQ_F32 if precision == "f32" else L.BQ_F64,
+                   L.BQ_MODEL_LS if model == "ls" else L.BQ_MODEL_BORN,
+                   float(tol), int(max_iter), L.BQ_FLAG_PLAIN if plain else 0)
+        ill = (L.Illum * self.L)(*[L.Illum(*row) for row in d])
+        self._stream = stream
+        h = ct.c_void_p()
+        s = self._lib.bq_create(ct.byref(g), ill, self.L, _stream_handle(stream), ct.byref(h))
+        if s != L.BQ_OK:
+            raise BQError(s, self._lib.bq_last_error(None).decode())
+        self._h = h
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s):
+        if s < 0:
+            raise BQError(s, self._lib.bq_last_error(self._h).decode())
+        return s
+
+    def _real(self, x: torch.Tensor, shape) -> torch.Tensor:
+        if x.dtype != self.rdtype or x.device.type != "cuda" or tuple(x.shape) != tuple(shape):
+            raise ValueError(f"expected {self.rdtype} cuda tensor of shape {shape}")
+        return x.contiguous()
+
+    def _cplx(self, v: torch.Tensor, shape) -> torch.Tensor:
+        if v.dtype != self.cdtype or v.device.type != "cuda" or tuple(v.shape) != tuple(shape):
+            raise ValueError(f"expected {self.cdtype} cuda tensor of shape {shape}")
+        return v.contiguous()
+
+    @staticmethod
+    def _idx(idx):
+        a = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1))
+        return a, a.ctypes.data_as(ct.POINTER(ct.c_int)), a.size
+
+    # ------------------------------------------------------------------
+    def forward(self, x: torch.Tensor, idx):
+        N = self.N
+        x = self._real(x, (N, N, N))
+        a, pidx, B = self._idx(idx)
+        y = torch.empty((B, N, N), dtype=self.cdtype, device=x.device)
+        st = (L.SolveStats * B)()
+        s = self._check(self._lib.bq_forward(self._h, _ptr(x), pidx, B, _ptr(y), st))
+        return y, _stats(st, B, s)
+
+    def fields(self, x: torch.Tensor, idx):
+        N = self.N
+        x = self._real(x, (N, N, N))
+        a, pidx, B = self._idx(idx)
+        u = torch.empty((B, N, N, N), dtype=self.cdtype, device=x.device)
+        st = (L.SolveStats * B)()
+        s = self._check(self._lib.bq_fields(self._h, _ptr(x), pidx, B, _ptr(u), st))
+        return u, _stats(st, B, s)
+
+    def grad(self, x: torch.Tensor, y: torch.Tensor, idx, scale: float,
+             out: torch.Tensor | None = None):
+        N = self.N
+        x = self._real(x, (N, N, N))
+        a, pidx, B = self._idx(idx)
+        y = self._cplx(y, (B, N, N))
+        g = torch.empty((N, N, N), dtype=self.rdtype, device=x.device) if out is None else out
+        loss = ct.c_double(0.0)
+        st = (L.SolveStats * B)()
+        s = self._check(self._lib.bq_grad(self._h, _ptr(x), _ptr(y), pidx, B, float(scale),
+                                          _ptr(g), ct.byref(loss), st))
+        return g, loss.value, _stats(st, B, s)
+
+    def green(self, v: torch.Tensor, adjoint: bool = False) -> torch.Tensor:
+        N = self.N
+        if v.dim() == 3:
+            v = v.unsqueeze(0)
+        B = v.shape[0]
+        v = self._cplx(v, (B, N, N, N))
+        out = torch.empty_like(v)
+        self._check(self._lib.bq_green_apply(self._h, _ptr(v), _ptr(out), B, int(bool(adjoint))))
+        return out
+
+
+@dataclass
+class ProxInfo:
+    newton_total: int
+    newton_max: int
+    beta_last: float
+    phi_last: float
+
+
+class WProx:
+    """Weighted proximal mapping of constrained TV on a fixed image shape."""
+
+    def __init__(self, shape, precision: str = "f32", stream: torch.cuda.Stream | None = None):
+        self._lib = L.load()
+        self.shape = tuple(int(s) for s in shape)
+        self.rdtype = torch.float32 if precision == "f32" else torch.float64
+        h = ct.c_void_p()
+        s = self._lib.bq_prox_create(*self.shape, L.BQ_F32 if precision == "f32" else L.BQ_F64,
+                                     _stream_handle(stream), ct.byref(h))
+        if s != L.BQ_OK:
+            raise BQError(s, self._lib.bq_prox_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bq_prox_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __call__(self, v: torch.Tensor, tau: float, u: torch.Tensor | None, lam: float,
+                 tv: str = "iso", cset: str = "nonneg", n_iter: int = 50,
+                 P: torch.Tensor | None = None, out: torch.Tensor | None = None):
+        for t in (v, u, P):
+            if t is not None and (t.dtype != self.rdtype or t.device.type != "cuda"):
+                raise ValueError(f"expected {self.rdtype} cuda tensors")
+        if tuple(v.shape) != self.shape:
+            raise ValueError("v has the wrong shape")
+        if u is not None and tuple(u.shape) != self.shape:
+            raise ValueError("u has the wrong shape")
+        if P is not None and tuple(P.shape) != (3,) + self.shape:
+            raise ValueError("P must have shape (3,) + image shape")
+        v = v.contiguous()
+        u = None if u is None else u.contiguous()
+        x = torch.empty_like(v) if out is None else out
+        st = L.ProxStats()
+        s = self._lib.bq_wprox(self._h, _ptr(v), float(tau), _ptr(u), float(lam),
+                               L.BQ_TV_ISO if tv == "iso" else L.BQ_TV_ANISO,
+                               L.BQ_SET_NONNEG if cset == "nonneg" else L.BQ_SET_NONE,
+                               int(n_iter), _ptr(x), _ptr(P), ct.byref(st))
+        if s < 0:
+            raise BQError(s, self._lib.bq_prox_last_error(self._h).decode())
+        return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last)

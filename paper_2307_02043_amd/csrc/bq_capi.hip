@@ -1,0 +1,517 @@
+// C ABI of the bq library: contexts, argument checking, and the host-side
+// driver of the batched and per-illumination ("plain") solve paths.
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bq.h"
+#include "bq_kernels.h"
+
+using namespace bq;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+bool supported_N(int N) {
+  switch (N) {
+    case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 256:
+      return true;
+    default:
+      return false;
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct bq_ctx {
+  bq_geom g{};
+  int L = 0;
+  std::vector<bq_illum> dirs;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double kb = 0.0;
+  size_t V = 0;
+  size_t csz = 0;  // bytes per complex element
+  int np_mv = 0, np_vec = 0, np_det = 0;
+  int Bcap = 0;
+  // device memory
+  void* ghat = nullptr;
+  void* twN = nullptr;
+  void* twH = nullptr;
+  void* f[8] = {};  // u w r rhat p v s t
+  void* zh = nullptr;
+  void* xh = nullptr;
+  void* rdet = nullptr;
+  C<double>* inc = nullptr;
+  SysState* state = nullptr;
+  double* part_mv = nullptr;
+  double* part_vec = nullptr;
+  double* part_det = nullptr;
+  std::vector<SysState> hstate;
+  std::vector<C<double>> hinc;
+};
+
+namespace {
+
+enum { F_U = 0, F_W, F_R, F_RHAT, F_P, F_V, F_S, F_T };
+
+bq_status set_err(bq_ctx* c, bq_status s, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return s;
+}
+
+bq_status hip_err(bq_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
+  return set_err(c, BQ_EDEVICE, m);
+}
+
+#define HIPCHK(c, call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_err(c, e_, #call);  \
+  } while (0)
+
+void free_batch(bq_ctx* c) {
+  for (auto& p : c->f) { if (p) (void)hipFree(p); p = nullptr; }
+  void** others[] = {&c->zh, &c->xh, &c->rdet, (void**)&c->inc, (void**)&c->state,
+                     (void**)&c->part_mv, (void**)&c->part_vec, (void**)&c->part_det};
+  for (void** p : others) { if (*p) (void)hipFree(*p); *p = nullptr; }
+  c->Bcap = 0;
+}
+
+bq_status ensure_capacity(bq_ctx* c, int B) {
+  if (B <= c->Bcap) return BQ_OK;
+  free_batch(c);
+  const size_t fb = (size_t)B * c->V * c->csz;
+  for (auto& p : c->f)
+    if (hipMalloc(&p, fb) != hipSuccess) { free_batch(c); return set_err(c, BQ_ENOMEM, "out of device memory (fields)"); }
+  if (hipMalloc(&c->zh, 2 * fb) != hipSuccess || hipMalloc(&c->xh, 4 * fb) != hipSuccess ||
+      hipMalloc(&c->rdet, (size_t)B * c->g.N * c->g.N * c->csz) != hipSuccess ||
+      hipMalloc((void**)&c->inc, (size_t)B * 3 * c->g.N * sizeof(C<double>)) != hipSuccess ||
+      hipMalloc((void**)&c->state, (size_t)B * sizeof(SysState)) != hipSuccess ||
+      hipMalloc((void**)&c->part_mv, (size_t)B * c->np_mv * 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&c->part_vec, (size_t)B * c->np_vec * 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&c->part_det, (size_t)B * c->np_det * sizeof(double)) != hipSuccess) {
+    free_batch(c);
+    return set_err(c, BQ_ENOMEM, "out of device memory (workspace)");
+  }
+  c->Bcap = B;
+  c->hstate.resize(B);
+  return BQ_OK;
+}
+
+// Plane-wave factors exp(i kb d_a c_i), c_i = (i - (N-1)/2) h, per system.
+bq_status upload_incident(bq_ctx* c, const int* idx, int B) {
+  const int N = c->g.N;
+  c->hinc.resize((size_t)B * 3 * N);
+  for (int b = 0; b < B; ++b) {
+    const bq_illum& d = c->dirs[idx[b]];
+    const double comp[3] = {d.dx, d.dy, d.dz};
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < N; ++i) {
+        const long double ci = ((long double)i - (N - 1) / 2.0L) * (long double)c->g.h_um;
+        const long double ph = (long double)c->kb * (long double)comp[a] * ci;
+        c->hinc[((size_t)b * 3 + a) * N + i] = C<double>{(double)cosl(ph), (double)sinl(ph)};
+      }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->inc, c->hinc.data(), c->hinc.size() * sizeof(C<double>),
+                           hipMemcpyHostToDevice, c->stream));
+  return BQ_OK;
+}
+
+template <typename T>
+PassArgs<T> pass_args(bq_ctx* c, int B, const C<double>* inc) {
+  PassArgs<T> a{};
+  a.N = c->g.N;
+  a.B = B;
+  a.mask = RUN_ALL;
+  a.state = c->state;
+  a.inc = inc;
+  a.zh = (C<T>*)c->zh;
+  a.xh = (C<T>*)c->xh;
+  a.ghat = (const C<T>*)c->ghat;
+  a.twN = (const C<T>*)c->twN;
+  a.twH = (const C<T>*)c->twH;
+  a.partial = c->part_mv;
+  return a;
+}
+
+template <typename T>
+VecArgs<T> vec_args(bq_ctx* c, int B, int sys0, void* e) {
+  VecArgs<T> v{};
+  v.B = B;
+  v.V = c->V;
+  v.N = c->g.N;
+  v.state = c->state;
+  const size_t off = (size_t)sys0 * c->V;
+  v.e = (C<T>*)e;
+  v.r = (C<T>*)c->f[F_R] + off;
+  v.rhat = (C<T>*)c->f[F_RHAT] + off;
+  v.p = (C<T>*)c->f[F_P] + off;
+  v.v = (C<T>*)c->f[F_V] + off;
+  v.s = (C<T>*)c->f[F_S] + off;
+  v.t = (C<T>*)c->f[F_T] + off;
+  v.partial = c->part_vec;
+  return v;
+}
+
+bq_status check_launch(bq_ctx* c, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, where);
+  return BQ_OK;
+}
+
+// BiCGSTAB for B systems (I - G diag(x)) e_b = b_b.
+//   fwd:  b = u_in (generated), e = u_in on entry (written here)
+//   !fwd: b = e on entry (already computed)
+template <typename T>
+bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, bool fwd, bool plain) {
+  const int N = c->g.N;
+  PassArgs<T> a = pass_args<T>(c, B, inc);
+  VecArgs<T> va = vec_args<T>(c, B, 0, e);
+  a.xpot = x;
+  // r0 = b - A e0 = G(x . e0) with e0 = b; rhat = r0
+  double bfix = 0.0;
+  const double* part_b = nullptr;
+  if (fwd) {
+    vec_fill_incident<T>(B, N, inc, (C<T>*)e, c->stream);
+    a.zf_mode = ZF_XUIN;
+    bfix = (double)c->V;  // |u_in| = 1 at every voxel
+  } else {
+    vec_norm<T>(va, (const C<T>*)e, c->stream);
+    part_b = c->part_vec;
+    a.zf_mode = ZF_XV;
+    a.vin = (const C<T>*)e;
+  }
+  a.zi_mode = ZI_G_NORM;
+  a.out = va.r;
+  a.out2 = va.rhat;
+  a.mask = RUN_ALL;
+  if (green_apply<T>(a, c->stream)) return check_launch(c, "green_apply(init)");
+  sc_init(B, c->state, c->part_mv, c->np_mv, part_b, c->np_vec, bfix, c->g.tol, c->g.max_iter, c->stream);
+  if (bq_status s = check_launch(c, "init")) return s;
+
+  const int chunk = plain ? 1 : 4;
+  const int max_loops = c->g.max_iter + 2;
+  for (int it = 0; it < max_loops; it += chunk) {
+    for (int k = 0; k < chunk; ++k) {
+      sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
+      vec_p<T>(va, c->stream);
+      a.mask = RUN_ACTIVE;
+      a.zf_mode = ZF_XV;
+      a.vin = va.p;
+      a.zi_mode = ZI_AV_RHAT;
+      a.vz = va.p;
+      a.rhat = va.rhat;
+      a.out = va.v;
+      a.out2 = nullptr;
+      green_apply<T>(a, c->stream);
+      sc_alpha(B, c->state, c->part_mv, c->np_mv, c->stream);
+      vec_s<T>(va, c->stream);
+      sc_s(B, c->state, c->part_vec, c->np_vec, c->stream);
+      a.mask = RUN_ACTIVE_NOT_S;
+      a.vin = va.s;
+      a.zi_mode = ZI_AS_TS;
+      a.vz = va.s;
+      a.out = va.t;
+      green_apply<T>(a, c->stream);
+      sc_omega(B, c->state, c->part_mv, c->np_mv, c->stream);
+      vec_xr<T>(va, c->stream);
+    }
+    if (bq_status s = check_launch(c, "bicgstab iteration")) return s;
+    HIPCHK(c, hipMemcpyAsync(c->hstate.data(), c->state, B * sizeof(SysState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool running = false;
+    for (int b = 0; b < B; ++b) running |= (c->hstate[b].status == SYS_RUNNING);
+    if (!running) break;
+  }
+  // a system still running after max_iter + 2 loops cannot happen (sc_beta
+  // stops at max_iter); treat it as not converged defensively
+  return BQ_OK;
+}
+
+int status_code(int s) {
+  switch (s) {
+    case SYS_CONVERGED: return 0;
+    case SYS_NOTCONV: return 1;
+    case SYS_BREAKDOWN: return 2;
+    default: return 3;
+  }
+}
+
+bq_status summarize(bq_ctx* c, const std::vector<bq_solve_stats>& st) {
+  int worst = 0;
+  for (const auto& s : st) {
+    const int a = s.status_fwd, b = s.status_adj;
+    const int m = a > b ? a : b;
+    if (m > worst) worst = m;
+  }
+  if (worst == 0) return BQ_OK;
+  const bq_status w = worst == 1 ? BQ_NOTCONV : worst == 2 ? BQ_BREAKDOWN : BQ_NONFINITE;
+  c->err = worst == 1 ? "a solve reached max_iter" : worst == 2 ? "BiCGSTAB breakdown" : "non-finite values in a solve";
+  return w;
+}
+
+void record(bq_ctx* c, std::vector<bq_solve_stats>& st, int b0, int nb, bool fwd) {
+  for (int b = 0; b < nb; ++b) {
+    const SysState& s = c->hstate[b];
+    bq_solve_stats& o = st[b0 + b];
+    if (fwd) { o.iters_fwd = s.iters; o.status_fwd = status_code(s.status); o.relres_fwd = s.res; }
+    else { o.iters_adj = s.iters; o.status_adj = status_code(s.status); o.relres_adj = s.res; }
+  }
+}
+
+bq_status check_batch(bq_ctx* c, const int* idx, int B) {
+  if (!c) return BQ_EINVAL;
+  if (B < 1 || !idx) return set_err(c, BQ_EINVAL, "B must be >= 1 and idx non-NULL");
+  for (int b = 0; b < B; ++b)
+    if (idx[b] < 0 || idx[b] >= c->L) return set_err(c, BQ_EINVAL, "illumination index out of range");
+  return BQ_OK;
+}
+
+// Forward fields of systems [0, nb) into `u` (solve, or u_in for Born).
+template <typename T>
+bq_status forward_fields(bq_ctx* c, const T* x, int nb, void* u, bool plain) {
+  if (c->g.model == BQ_MODEL_BORN) {
+    vec_fill_incident<T>(nb, c->g.N, c->inc, (C<T>*)u, c->stream);
+    for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
+    return check_launch(c, "fill_incident");
+  }
+  return bicgstab<T>(c, nb, x, u, c->inc, true, plain);
+}
+
+template <typename T>
+bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out, bq_solve_stats* st,
+                     bool want_fields) {
+  if (bq_status s = check_batch(c, idx, B)) return s;
+  if (!x || !out) return set_err(c, BQ_EINVAL, "null device pointer");
+  const bool plain = (c->g.flags & BQ_FLAG_PLAIN) != 0;
+  if (bq_status s = ensure_capacity(c, plain ? 1 : B)) return s;
+  std::vector<bq_solve_stats> stats(B);
+  const int N = c->g.N;
+  const size_t N2 = (size_t)N * N;
+  const int step = plain ? 1 : B;
+  for (int b0 = 0; b0 < B; b0 += step) {
+    const int nb = plain ? 1 : B;
+    if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
+    void* u = want_fields ? (void*)((C<T>*)out + (size_t)b0 * c->V) : c->f[F_U];
+    if (c->g.model == BQ_MODEL_BORN && !want_fields) {
+      PassArgs<T> a = pass_args<T>(c, nb, c->inc);
+      a.xpot = (const T*)x;
+      a.zf_mode = ZF_XUIN;
+      a.zi_mode = ZI_G;
+      a.out = (C<T>*)c->f[F_V];
+      if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+      detector<T>(nb, N, (const C<T>*)c->f[F_V], 0, c->inc, nullptr, (C<T>*)out + (size_t)b0 * N2,
+                  nullptr, c->np_det, c->stream);
+      for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
+    } else {
+      if (bq_status s = forward_fields<T>(c, (const T*)x, nb, u, plain)) return s;
+      if (!want_fields)
+        detector<T>(nb, N, (const C<T>*)u, 1, c->inc, nullptr, (C<T>*)out + (size_t)b0 * N2, nullptr,
+                    c->np_det, c->stream);
+    }
+    if (bq_status s = check_launch(c, "forward")) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    record(c, stats, b0, nb, true);
+    for (int b = 0; b < nb; ++b) { stats[b0 + b].status_adj = 0; }
+  }
+  if (st) std::memcpy(st, stats.data(), B * sizeof(bq_solve_stats));
+  return summarize(c, stats);
+}
+
+template <typename T>
+bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, void* g,
+                  double* loss, bq_solve_stats* st) {
+  if (bq_status s = check_batch(c, idx, B)) return s;
+  if (!x || !y || !g) return set_err(c, BQ_EINVAL, "null device pointer");
+  const bool plain = (c->g.flags & BQ_FLAG_PLAIN) != 0;
+  if (bq_status s = ensure_capacity(c, plain ? 1 : B)) return s;
+  std::vector<bq_solve_stats> stats(B);
+  const int N = c->g.N;
+  const size_t N2 = (size_t)N * N;
+  const bool born = c->g.model == BQ_MODEL_BORN;
+  double total_loss = 0.0;
+  std::vector<double> hpart;
+  const int step = plain ? 1 : B;
+  for (int b0 = 0; b0 < B; b0 += step) {
+    const int nb = step;
+    if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
+    // forward field and detector residual r = S(u - u_in) - y
+    const C<T>* field;
+    int sub;
+    if (born) {
+      PassArgs<T> a = pass_args<T>(c, nb, c->inc);
+      a.xpot = (const T*)x;
+      a.zf_mode = ZF_XUIN;
+      a.zi_mode = ZI_G;
+      a.out = (C<T>*)c->f[F_V];
+      if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+      field = (const C<T>*)c->f[F_V];
+      sub = 0;
+      for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
+    } else {
+      if (bq_status s = bicgstab<T>(c, nb, (const T*)x, c->f[F_U], c->inc, true, plain)) return s;
+      field = (const C<T>*)c->f[F_U];
+      sub = 1;
+    }
+    record(c, stats, b0, nb, true);
+    detector<T>(nb, N, field, sub, c->inc, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det,
+                c->np_det, c->stream);
+    // adjoint right-hand side (conjugated): G S^T conj(r)
+    {
+      PassArgs<T> a = pass_args<T>(c, nb, c->inc);
+      a.rdet = (const C<T>*)c->rdet;
+      a.zf_mode = ZF_DETCONJ;
+      a.zi_mode = ZI_G;
+      a.out = (C<T>*)c->f[F_W];
+      if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+    }
+    if (born) {
+      for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
+    } else {
+      if (bq_status s = bicgstab<T>(c, nb, (const T*)x, c->f[F_W], c->inc, false, plain)) return s;
+    }
+    record(c, stats, b0, nb, false);
+    gradient<T>(nb, N, born ? nullptr : (const C<T>*)c->f[F_U], c->inc, (const C<T>*)c->f[F_W], scale,
+                b0 > 0 ? 1 : 0, (T*)g, c->stream);
+    if (bq_status s = check_launch(c, "grad")) return s;
+    hpart.resize((size_t)nb * c->np_det);
+    HIPCHK(c, hipMemcpyAsync(hpart.data(), c->part_det, hpart.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (double v : hpart) total_loss += v;
+  }
+  if (loss) *loss = scale * total_loss;
+  if (st) std::memcpy(st, stats.data(), B * sizeof(bq_solve_stats));
+  return summarize(c, stats);
+}
+
+template <typename T>
+bq_status do_green(bq_ctx* c, const void* v, void* out, int B, int adjoint) {
+  if (!c) return BQ_EINVAL;
+  if (!v || !out || B < 1) return set_err(c, BQ_EINVAL, "null pointer or B < 1");
+  if (bq_status s = ensure_capacity(c, B)) return s;
+  PassArgs<T> a = pass_args<T>(c, B, nullptr);
+  a.vin = (const C<T>*)v;
+  a.zf_mode = adjoint ? ZF_VCONJ : ZF_V;
+  a.zi_mode = adjoint ? ZI_GCONJ : ZI_G;
+  a.out = (C<T>*)out;
+  a.state = nullptr;
+  if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+  if (bq_status s = check_launch(c, "green_apply")) return s;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BQ_OK;
+}
+
+template <typename T>
+bq_status create_tables(bq_ctx* c) {
+  const int N = c->g.N;
+  std::vector<C<T>> tn(N), th(N);
+  for (int k = 0; k < N; ++k) {
+    const double a = -2.0 * k / N, b = -(double)k / N;
+    tn[k] = C<T>{(T)cospi_host(a), (T)sinpi_host(a)};
+    th[k] = C<T>{(T)cospi_host(b), (T)sinpi_host(b)};
+  }
+  HIPCHK(c, hipMalloc(&c->twN, N * sizeof(C<T>)));
+  HIPCHK(c, hipMalloc(&c->twH, N * sizeof(C<T>)));
+  HIPCHK(c, hipMemcpy(c->twN, tn.data(), N * sizeof(C<T>), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->twH, th.data(), N * sizeof(C<T>), hipMemcpyHostToDevice));
+  if (hipMalloc(&c->ghat, 8 * c->V * sizeof(C<T>)) != hipSuccess)
+    return set_err(c, BQ_ENOMEM, "out of device memory (transfer function)");
+  const int rc = ghat_precompute<T>(N, c->g.h_um, c->kb, (C<T>*)c->ghat, c->stream);
+  if (rc == -3) return set_err(c, BQ_ENOMEM, "out of device memory (kernel precomputation)");
+  if (rc != 0) return set_err(c, BQ_EDEVICE, "kernel precomputation failed");
+  c->np_mv = green_num_partials<T>(N);
+  return BQ_OK;
+}
+
+void destroy_ctx(bq_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_batch(c);
+  if (c->ghat) (void)hipFree(c->ghat);
+  if (c->twN) (void)hipFree(c->twN);
+  if (c->twH) (void)hipFree(c->twH);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+bq_status bq_create(const bq_geom* g, const bq_illum* dirs, int L, void* stream, bq_ctx** out) {
+  if (!out) return set_err(nullptr, BQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!g || !dirs || L < 1) return set_err(nullptr, BQ_EINVAL, "geometry/directions missing or L < 1");
+  if (!supported_N(g->N)) return set_err(nullptr, BQ_EUNSUPPORTED, "unsupported grid size N");
+  if (!(g->h_um > 0) || !(g->lambda0_um > 0) || !(g->n_b > 0) || !(g->tol >= 0) || g->max_iter < 0)
+    return set_err(nullptr, BQ_EINVAL, "h, lambda0, n_b must be > 0; tol, max_iter >= 0");
+  if (g->precision != BQ_F32 && g->precision != BQ_F64) return set_err(nullptr, BQ_EINVAL, "precision");
+  if (g->model != BQ_MODEL_LS && g->model != BQ_MODEL_BORN) return set_err(nullptr, BQ_EINVAL, "model");
+  for (int l = 0; l < L; ++l) {
+    const double n2 = dirs[l].dx * dirs[l].dx + dirs[l].dy * dirs[l].dy + dirs[l].dz * dirs[l].dz;
+    if (!(fabs(n2 - 1.0) < 2e-6)) return set_err(nullptr, BQ_EINVAL, "illumination direction is not a unit vector");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_err(nullptr, BQ_EDEVICE, "no HIP device");
+  bq_ctx* c = new bq_ctx();
+  c->g = *g;
+  c->L = L;
+  c->dirs.assign(dirs, dirs + L);
+  c->stream = (hipStream_t)stream;
+  c->kb = 2.0 * M_PI * g->n_b / g->lambda0_um;
+  c->V = (size_t)g->N * g->N * g->N;
+  c->csz = g->precision == BQ_F32 ? sizeof(C<float>) : sizeof(C<double>);
+  c->np_vec = vec_num_partials(c->V);
+  c->np_det = det_num_partials(g->N);
+  bq_status s = g->precision == BQ_F32 ? create_tables<float>(c) : create_tables<double>(c);
+  if (s != BQ_OK) {
+    g_create_error = c->err;
+    destroy_ctx(c);
+    return s;
+  }
+  *out = c;
+  return BQ_OK;
+}
+
+bq_status bq_destroy(bq_ctx* ctx) {
+  destroy_ctx(ctx);
+  return BQ_OK;
+}
+
+const char* bq_last_error(const bq_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+bq_status bq_forward(bq_ctx* c, const void* x, const int* idx, int B, void* y_out, bq_solve_stats* st) {
+  if (!c) return BQ_EINVAL;
+  return c->g.precision == BQ_F32 ? do_forward<float>(c, x, idx, B, y_out, st, false)
+                                  : do_forward<double>(c, x, idx, B, y_out, st, false);
+}
+
+bq_status bq_fields(bq_ctx* c, const void* x, const int* idx, int B, void* u_out, bq_solve_stats* st) {
+  if (!c) return BQ_EINVAL;
+  return c->g.precision == BQ_F32 ? do_forward<float>(c, x, idx, B, u_out, st, true)
+                                  : do_forward<double>(c, x, idx, B, u_out, st, true);
+}
+
+bq_status bq_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, void* g_out,
+                  double* loss, bq_solve_stats* st) {
+  if (!c) return BQ_EINVAL;
+  return c->g.precision == BQ_F32 ? do_grad<float>(c, x, y, idx, B, scale, g_out, loss, st)
+                                  : do_grad<double>(c, x, y, idx, B, scale, g_out, loss, st);
+}
+
+bq_status bq_green_apply(bq_ctx* c, const void* v, void* out, int B, int adjoint) {
+  if (!c) return BQ_EINVAL;
+  return c->g.precision == BQ_F32 ? do_green<float>(c, v, out, B, adjoint)
+                                  : do_green<double>(c, v, out, B, adjoint);
+}
+
+}  // extern "C"

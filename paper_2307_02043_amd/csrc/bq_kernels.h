@@ -1,0 +1,66 @@
+// Host-side declarations of the kernel launchers of the bq library.
+#pragma once
+
+#include <cmath>
+#include <vector>
+
+#include "bq_state.h"
+
+namespace bq {
+
+// exp(-2 pi i k / len) style twiddles are built on the host in long double
+// and rounded once, so FP32 and FP64 tables are correctly rounded.
+inline double cospi_host(double a) { return (double)cosl(3.14159265358979323846264338327950288L * (long double)a); }
+inline double sinpi_host(double a) { return (double)sinl(3.14159265358979323846264338327950288L * (long double)a); }
+
+// ---- Green's operator ----------------------------------------------------
+template <typename T> int green_apply(const PassArgs<T>& a, hipStream_t st);
+template <typename T> int green_num_partials(int N);
+template <typename T> int ghat_precompute(int N, double h, double kb, C<T>* out, hipStream_t st);
+int ghat_oversampling(int N);
+
+// ---- BiCGSTAB and the data term -------------------------------------------
+constexpr int VEC_WG = 256;  // threads per workgroup of the vector kernels
+int vec_num_partials(size_t V);
+
+template <typename T> struct VecArgs {
+  int B;
+  size_t V;
+  int N;
+  SysState* state;
+  C<T>* e;       // iterate (u or w-bar)
+  C<T>* r;
+  C<T>* rhat;
+  C<T>* p;
+  C<T>* v;
+  C<T>* s;
+  C<T>* t;
+  double* partial;  // B x NPV x 4
+};
+
+template <typename T> void vec_p(const VecArgs<T>& a, hipStream_t st);
+template <typename T> void vec_s(const VecArgs<T>& a, hipStream_t st);
+template <typename T> void vec_xr(const VecArgs<T>& a, hipStream_t st);
+template <typename T> void vec_norm(const VecArgs<T>& a, const C<T>* f, hipStream_t st);
+template <typename T> void vec_fill_incident(int B, int N, const C<double>* inc, C<T>* out, hipStream_t st);
+
+void sc_init(int B, SysState* st, const double* part_r, int np_r, const double* part_b, int np_b,
+             double bnorm2_fixed, double tol, int max_iter, hipStream_t s);
+void sc_beta(int B, SysState* st, const double* part, int np, hipStream_t s);
+void sc_alpha(int B, SysState* st, const double* part, int np, hipStream_t s);
+void sc_s(int B, SysState* st, const double* part, int np, hipStream_t s);
+void sc_omega(int B, SysState* st, const double* part, int np, hipStream_t s);
+
+// Detector: H = S(field - u_in) (subtract_uin) or S(field); if ymeas is given
+// writes r = H - y to out and FP64 partials of |r|^2 / 2, else writes H.
+template <typename T>
+void detector(int B, int N, const C<T>* field, int subtract_uin, const C<double>* inc,
+              const C<T>* ymeas, C<T>* out, double* partial, int np, hipStream_t st);
+int det_num_partials(int N);
+
+// g (+)= scale * sum_b Re(u_b . wbar_b); u_b generated from inc if u == null.
+template <typename T>
+void gradient(int B, int N, const C<T>* u, const C<double>* inc, const C<T>* wbar, double scale,
+              int accumulate, T* g, hipStream_t st);
+
+}  // namespace bq

@@ -1,0 +1,89 @@
+// Per-system BiCGSTAB state kept in device memory (all scalars FP64), and
+// the argument blocks of the Green's-operator passes.
+#pragma once
+
+#include "bq_common.h"
+
+namespace bq {
+
+enum SysStatus : int {
+  SYS_RUNNING = 0,
+  SYS_CONVERGED = 1,
+  SYS_NOTCONV = 2,
+  SYS_BREAKDOWN = 3,
+  SYS_NONFINITE = 4,
+};
+
+struct SysState {
+  double rho_x, rho_y;          // rho = <rhat, r> of the previous iteration
+  double rhon_x, rhon_y;        // rho_new
+  double alpha_x, alpha_y;
+  double omega_x, omega_y;
+  double beta_x, beta_y;
+  double bnorm2;                // ||b||^2
+  double res;                   // last relative (recursive) residual
+  int status;
+  int iters;
+  int sflag;                    // converged on the half step ||s||
+  int first;                    // no iteration done yet
+  double tol;
+  int max_iter;
+  int pad_;
+};
+
+// Which systems a solver pass works on.
+enum RunMask : int { RUN_ALL = 0, RUN_ACTIVE = 1, RUN_ACTIVE_NOT_S = 2 };
+
+__device__ inline bool sys_skip(const SysState* st, int mask, int b) {
+  if (mask == RUN_ALL || st == nullptr) return false;
+  const SysState& s = st[b];
+  if (s.status != SYS_RUNNING) return true;
+  if (mask == RUN_ACTIVE_NOT_S && s.sflag) return true;
+  return false;
+}
+
+// Prologue of the forward z pass: what field the Green's operator acts on.
+enum ZfMode : int {
+  ZF_XV = 0,       // x . v
+  ZF_XUIN = 1,     // x . u_in (plane wave generated in-register)
+  ZF_DETCONJ = 2,  // S^T conj(r_det): conj of the detector image on z = N-1
+  ZF_V = 3,        // v
+  ZF_VCONJ = 4,    // conj(v)
+};
+
+// Epilogue of the inverse z pass.
+enum ZiMode : int {
+  ZI_G = 0,         // out = G w
+  ZI_GCONJ = 1,     // out = conj(G w)
+  ZI_AV_RHAT = 2,   // out = v - G w ; partial <rhat, out>
+  ZI_AS_TS = 3,     // out = s - G w ; partials <out, s>, <out, out>
+  ZI_G_NORM = 4,    // out = out2 = G w ; partial ||out||^2
+};
+
+template <typename T>
+struct PassArgs {
+  int N, B;
+  int mask;                    // RunMask
+  const SysState* state;
+  // z-forward prologue
+  int zf_mode;
+  const T* xpot;               // scattering potential, N^3 real
+  const C<T>* vin;             // B x N^3
+  const C<T>* rdet;            // B x N^2 detector residual
+  const C<double>* inc;        // B x 3 x N plane-wave factors (x, y, z)
+  // intermediates
+  C<T>* zh;                    // B x 2 x N^3
+  C<T>* xh;                    // B x 4 x N^3 (split xy path)
+  const C<T>* ghat;            // 8 x N^3 parity-class transfer function
+  const C<T>* twN;             // W_N^k, k < N
+  const C<T>* twH;             // exp(-i pi n / N), n < N
+  // z-inverse epilogue
+  int zi_mode;
+  const C<T>* vz;              // v (ZI_AV_RHAT) or s (ZI_AS_TS)
+  const C<T>* rhat;
+  C<T>* out;
+  C<T>* out2;
+  double* partial;             // B x NP x 4
+};
+
+}  // namespace bq
