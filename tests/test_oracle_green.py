@@ -146,9 +146,10 @@ def test_oversampling_needed_for_radiating_sources():
     pts += [(0, 0, 0), (N - 1, N - 1, N - 1), (0, N - 1, 0)]
     ref = np.array([_radial_solution(float(rr[p]), KB, sigma) for p in pts])
     errs = {}
-    for Q in (2 * N, 4 * N):
+    for Q in (2 * N, 3 * N, 4 * N):
         u = green.apply_G(green.kernel_padded(N, H, KB, Q=Q), rho)
         got = np.array([u[p] for p in pts])
         errs[Q] = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert errs[4 * N] < 1e-7, errs
+    assert errs[3 * N] < 1e-7, errs      # the rule used above N = 128
     assert errs[2 * N] > 1e-1, errs
