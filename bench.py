@@ -1,0 +1,227 @@
+#!/usr/bin/env python
+"""Benchmark of the mini-batch Lippmann-Schwinger gradient on one MI355X.
+
+One step = one call of the library's batched mini-batch gradient
+(forward solves, detector residual, adjoint solves, gradient reduction) over
+one mini-batch of synthetic data, inputs already resident in HBM.
+
+Default workload: 128^3 grid (256^3 padded), mini-batch of 16 out of 120
+illuminations, complex64 fields with FP64 reductions, BiCGSTAB tol 1e-5.
+The same inputs are also run through the plain path (FP64, one illumination
+at a time, host round trip per iteration) and through the CPU oracle on a
+bounded sample, and the JSON line reports the dominant kernel against the
+HBM roofline.
+
+Measurements: the phantom, illuminations and mini-batch come from the
+seeded synthetic generators; the measured fields y are produced by the
+library's own FP32 forward model on the phantom (tol 1e-6) plus 30 dB
+noise.  They only set up a realistic residual for timing; no parity claim
+rests on them.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LS gradient illum-solves/sec at 128^3 (batched FP32 vs plain FP64), % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes of one pass for one system and one application of G,
+# in units of V = N^3 complex elements (x the complex element size).  The
+# z passes depend on the prologue/epilogue; the figures are those of the
+# solver matvecs, which are the bulk of the launches.
+PASS_UNITS = {
+    "zf": 3.5,   # read v (1) + x (real, 0.5); write 2 parity classes (2)
+    "xf": 6.0,   # read 2, write 4
+    "yc": 16.0,  # read 4, write 4, transfer function 8 (once per system)
+    "xi": 6.0,   # read 4, write 2
+    "zi": 5.0,   # read 2 + v/s (1) + rhat or s (1); write 1
+    "xy": 12.0,  # fused plane pass: read 2, write 2, transfer function 8
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4_ls128_f32")
+    ap.add_argument("--plain-steps", type=int, default=1,
+                    help="timed steps of the plain FP64 path (0: skip)")
+    ap.add_argument("--cpu-iters", type=int, default=10,
+                    help="BiCGSTAB iterations of the oracle sample (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the gradient would shard by illuminations with one all-reduce "
+              "of the N^3 gradient, which is not built here).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synthetic as syn
+    from paper_2307_02043_amd import LSContext
+    from paper_2307_02043_amd import _lib as L
+
+    w = syn.WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    N, B = w.N, w.B
+    V = N ** 3
+    log(f"workload {w.name}: N={N} B={B} of L={w.L}")
+    xt = syn.scattering_potential(syn.make_phantom(w))
+    dirs = syn.workload_directions(w)
+    idx = syn.batch_indices(w)
+    scale = 1.0 / B
+
+    # measurements from the library's own forward model + noise
+    t = time.perf_counter()
+    fwd = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=1e-6,
+                    max_iter=w.max_iter)
+    yc, _ = fwd.forward(torch.from_numpy(xt).to(dev, torch.float32), idx)
+    fwd.close()
+    y = syn.add_noise(yc.cpu().numpy(), w.snr_db, np.random.default_rng(w.seed("noise")))
+    log(f"measurements ready ({time.perf_counter() - t:.1f} s)")
+
+    # ---- batched FP32 path ------------------------------------------------
+    t = time.perf_counter()
+    ctx = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol,
+                    max_iter=w.max_iter)
+    setup_s = time.perf_counter() - t
+    lib = L.load()
+    xe = torch.from_numpy(0.5 * xt).to(dev, torch.float32)
+    yt = torch.from_numpy(y).to(dev, torch.complex64)
+    for i in range(args.warmup):
+        _, loss, info = ctx.grad(xe, yt, idx, scale)
+        log(f"warmup {i}: loss {loss:.6e} iters fwd {info.iters_fwd} adj {info.iters_adj}")
+    torch.cuda.synchronize()
+    lib.bq_timing(ctx._h, 1)
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        g, loss, info = ctx.grad(xe, yt, idx, scale)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.bq_timing(ctx._h, 0)
+    elapsed = t1 - t0
+    log(f"batched f32: {args.steps} steps in {elapsed:.3f} s")
+    pass_ms, pass_n = {}, {}
+    for pid, name in enumerate(L.PASS_NAMES):
+        ms = L.ct.c_double()
+        n = L.ct.c_longlong()
+        lib.bq_timing_get(ctx._h, pid, L.ct.byref(ms), L.ct.byref(n))
+        if n.value:
+            pass_ms[name], pass_n[name] = ms.value, n.value
+    apps = sum(sum(inf.green_apps) for inf in infos)
+    iters = sum(sum(inf.iters_fwd) + sum(inf.iters_adj) for inf in infos)
+    value = B * args.steps / elapsed
+    status = max(inf.status for inf in infos)
+
+    # roofline of the dominant pass
+    dom = max((k for k in pass_ms if k in PASS_UNITS), key=lambda k: pass_ms[k])
+    csz = 8  # complex64
+    alg_bytes = apps * PASS_UNITS[dom] * V * csz
+    achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": f"k_{dom}<float,{N}>", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "bytes_per_system_application": PASS_UNITS[dom] * V * csz,
+                "system_applications": apps, "launches": pass_n[dom],
+                "avg_launch_ms": round(pass_ms[dom] / pass_n[dom], 4)}
+    ctx.close()
+
+    # ---- plain FP64 path ----------------------------------------------------
+    plain = None
+    if args.plain_steps > 0:
+        ctx64 = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f64", "ls", tol=w.tol,
+                          max_iter=w.max_iter, plain=True)
+        x64 = torch.from_numpy(0.5 * xt).to(dev)
+        y64 = torch.from_numpy(y).to(dev)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        pinfos = []
+        for i in range(args.plain_steps):
+            g64, loss64, pinfo = ctx64.grad(x64, y64, idx, scale)
+            pinfos.append(pinfo)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - p0
+        piters = sum(sum(p.iters_fwd) + sum(p.iters_adj) for p in pinfos)
+        gerr = float(torch.linalg.norm(g.double() - g64) / torch.linalg.norm(g64))
+        plain = {"value": round(B * args.plain_steps / pel, 3), "unit": "illum-solves/s",
+                 "ms_per_step": round(pel / args.plain_steps * 1e3, 2), "steps": args.plain_steps,
+                 "bicgstab_iters_per_s": round(piters / pel, 1),
+                 "iters_per_step": piters / args.plain_steps,
+                 "f32_vs_f64_grad_rel_err": gerr}
+        log(f"plain f64: {pel:.2f} s, grad rel diff f32 vs f64 {gerr:.2e}")
+        ctx64.close()
+
+    # ---- CPU oracle baseline --------------------------------------------------
+    cpu = None
+    if args.cpu_iters > 0:
+        from oracle import lsmodel
+        cores = min(os.cpu_count() or 1, 16)
+        geom = lsmodel.Geometry(N=N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+        t = time.perf_counter()
+        model = lsmodel.LSModel(geom, workers=cores)
+        log(f"oracle transfer function ({time.perf_counter() - t:.1f} s)")
+        xe64 = 0.5 * xt
+        uin = lsmodel.incident_field(geom, dirs[idx[0]])
+        t = time.perf_counter()
+        model.solve_forward(xe64, uin, 0.0, args.cpu_iters)  # tol 0: runs the cap
+        t_iter = (time.perf_counter() - t) / args.cpu_iters
+        mean_iters = iters / (args.steps * B)
+        extra = 3  # initial residuals of both solves + adjoint right-hand side
+        t_ill = t_iter * mean_iters + extra * t_iter / 2
+        cpu = {"value": round(1.0 / t_ill, 5), "unit": "illum-solves/s", "cores": cores,
+               "kind": "oracle",
+               "sample": (f"one illumination of this workload: the oracle's FP64 BiCGSTAB run for "
+                          f"{args.cpu_iters} iterations ({t_iter:.2f} s each, scipy.fft with "
+                          f"{cores} workers), extrapolated to the GPU-observed "
+                          f"{mean_iters:.1f} iterations per illumination (forward + adjoint) plus "
+                          f"3 extra applications of G")}
+        log(f"oracle: {t_iter:.2f} s per BiCGSTAB iteration")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "illum-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"{w.name}: Lippmann-Schwinger mini-batch gradient, {N}^3 grid "
+                                f"({2 * N}^3 padded), batch {B} of {w.L} illuminations, complex64 "
+                                f"fields, FP64 reductions, BiCGSTAB tol {w.tol:g}"),
+                   "grid": N, "batch": B, "illuminations": w.L, "tol": w.tol},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain_f64": plain,
+        "speedup_vs_plain_f64": (round(value / plain["value"], 2) if plain else None),
+        "solver": {"status": status, "bicgstab_iters_per_step": iters / args.steps,
+                   "green_apps_per_step": apps / args.steps,
+                   "bicgstab_iters_per_s": round(iters / elapsed, 1), "setup_s": round(setup_s, 2)},
+        "passes_ms_per_step": {k: round(v / args.steps, 3) for k, v in pass_ms.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

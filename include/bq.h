@@ -89,6 +89,10 @@ typedef struct {
   int status_fwd, status_adj; /* 0 converged, 1 not converged, 2 breakdown,
                                  3 non-finite                               */
   double relres_fwd, relres_adj; /* final relative recursive residuals      */
+  int green_apps;             /* applications of G for this illumination in
+                                 the call (solver matvecs, initial
+                                 residuals, adjoint right-hand side)        */
+  int pad_;
 } bq_solve_stats;
 
 typedef struct bq_ctx bq_ctx;
@@ -141,6 +145,24 @@ bq_status bq_grad(bq_ctx* ctx, const void* x, const void* y, const int* idx, int
  * out_b = G v_b (adjoint != 0: G^H v_b).  v, out: device, B x N^3 complex;
  * v and out must not overlap. */
 bq_status bq_green_apply(bq_ctx* ctx, const void* v, void* out, int B, int adjoint);
+
+/* Device timing of the passes of the Green's operator (HIP events recorded
+ * on the context stream around every launch).  enable != 0 clears the
+ * counters and starts timing; 0 stops it.  bq_timing_get returns the summed
+ * duration (ms) and the number of launches of one pass since the last
+ * enable.  Errors: BQ_EINVAL. */
+typedef enum {
+  BQ_PASS_ZF = 0,  /* z lines, forward, with the input prologue          */
+  BQ_PASS_XF = 1,  /* x rows, forward (split path)                        */
+  BQ_PASS_YC = 2,  /* y columns: FFT, transfer function, inverse FFT      */
+  BQ_PASS_XI = 3,  /* x rows, inverse (split path)                        */
+  BQ_PASS_ZI = 4,  /* z lines, inverse, with the epilogue and partial sums */
+  BQ_PASS_XY = 5,  /* fused x/y plane pass (LDS-resident planes)          */
+  BQ_PASS_VEC = 6, /* BiCGSTAB vector updates                             */
+  BQ_PASS_COUNT = 7
+} bq_pass;
+bq_status bq_timing(bq_ctx* ctx, int enable);
+bq_status bq_timing_get(const bq_ctx* ctx, int pass, double* total_ms, long long* launches);
 
 /* ---------------------------------------------------------------------
  * Weighted proximal mapping of constrained TV

@@ -18,9 +18,10 @@ BQ_MODEL_LS, BQ_MODEL_BORN = 0, 1
 BQ_FLAG_PLAIN = 1
 BQ_TV_ISO, BQ_TV_ANISO = 0, 1
 BQ_SET_NONE, BQ_SET_NONNEG = 0, 1
+PASS_NAMES = ("zf", "xf", "yc", "xi", "zi", "xy", "vec")
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
-            "bq_grad", "bq_green_apply", "bq_prox_create", "bq_prox_destroy",
+            "bq_grad", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",
             "bq_prox_last_error", "bq_wprox")
 
 
@@ -37,7 +38,8 @@ class Illum(ct.Structure):
 class SolveStats(ct.Structure):
     _fields_ = [("iters_fwd", ct.c_int), ("iters_adj", ct.c_int),
                 ("status_fwd", ct.c_int), ("status_adj", ct.c_int),
-                ("relres_fwd", ct.c_double), ("relres_adj", ct.c_double)]
+                ("relres_fwd", ct.c_double), ("relres_adj", ct.c_double),
+                ("green_apps", ct.c_int), ("pad_", ct.c_int)]
 
 
 class ProxStats(ct.Structure):
@@ -66,6 +68,8 @@ def load() -> ct.CDLL:
         "bq_fields": ([P, P, ct.POINTER(I), I, P, ct.POINTER(SolveStats)], I),
         "bq_grad": ([P, P, P, ct.POINTER(I), I, D, P, ct.POINTER(D), ct.POINTER(SolveStats)], I),
         "bq_green_apply": ([P, P, P, I, I], I),
+        "bq_timing": ([P, I], I),
+        "bq_timing_get": ([P, I, ct.POINTER(D), ct.POINTER(ct.c_longlong)], I),
         "bq_prox_create": ([I, I, I, I, P, ct.POINTER(P)], I),
         "bq_prox_destroy": ([P], I),
         "bq_prox_last_error": ([P], ct.c_char_p),

@@ -31,6 +31,7 @@ class SolveInfo:
     status_adj: list
     relres_fwd: list
     relres_adj: list
+    green_apps: list
 
 
 def _stats(arr, B, status) -> SolveInfo:
@@ -39,7 +40,8 @@ def _stats(arr, B, status) -> SolveInfo:
                      [arr[i].status_fwd for i in range(B)],
                      [arr[i].status_adj for i in range(B)],
                      [arr[i].relres_fwd for i in range(B)],
-                     [arr[i].relres_adj for i in range(B)])
+                     [arr[i].relres_adj for i in range(B)],
+                     [arr[i].green_apps for i in range(B)])
 
 
 def _ptr(t: torch.Tensor | None):

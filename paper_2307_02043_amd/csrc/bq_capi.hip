@@ -56,6 +56,7 @@ struct bq_ctx {
   double* part_det = nullptr;
   std::vector<SysState> hstate;
   std::vector<C<double>> hinc;
+  PassTimer timer;
 };
 
 namespace {
@@ -194,7 +195,7 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
   a.out = va.r;
   a.out2 = va.rhat;
   a.mask = RUN_ALL;
-  if (green_apply<T>(a, c->stream)) return check_launch(c, "green_apply(init)");
+  if (green_apply<T>(a, c->stream, &c->timer)) return check_launch(c, "green_apply(init)");
   sc_init(B, c->state, c->part_mv, c->np_mv, part_b, c->np_vec, bfix, c->g.tol, c->g.max_iter, c->stream);
   if (bq_status s = check_launch(c, "init")) return s;
 
@@ -203,7 +204,9 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
   for (int it = 0; it < max_loops; it += chunk) {
     for (int k = 0; k < chunk; ++k) {
       sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
+      c->timer.start(P_VEC, c->stream);
       vec_p<T>(va, c->stream);
+      c->timer.stop(c->stream);
       a.mask = RUN_ACTIVE;
       a.zf_mode = ZF_XV;
       a.vin = va.p;
@@ -212,22 +215,27 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
       a.rhat = va.rhat;
       a.out = va.v;
       a.out2 = nullptr;
-      green_apply<T>(a, c->stream);
+      green_apply<T>(a, c->stream, &c->timer);
       sc_alpha(B, c->state, c->part_mv, c->np_mv, c->stream);
+      c->timer.start(P_VEC, c->stream);
       vec_s<T>(va, c->stream);
+      c->timer.stop(c->stream);
       sc_s(B, c->state, c->part_vec, c->np_vec, c->stream);
       a.mask = RUN_ACTIVE_NOT_S;
       a.vin = va.s;
       a.zi_mode = ZI_AS_TS;
       a.vz = va.s;
       a.out = va.t;
-      green_apply<T>(a, c->stream);
+      green_apply<T>(a, c->stream, &c->timer);
       sc_omega(B, c->state, c->part_mv, c->np_mv, c->stream);
+      c->timer.start(P_VEC, c->stream);
       vec_xr<T>(va, c->stream);
+      c->timer.stop(c->stream);
     }
     if (bq_status s = check_launch(c, "bicgstab iteration")) return s;
     HIPCHK(c, hipMemcpyAsync(c->hstate.data(), c->state, B * sizeof(SysState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->timer.collect();
     bool running = false;
     for (int b = 0; b < B; ++b) running |= (c->hstate[b].status == SYS_RUNNING);
     if (!running) break;
@@ -259,12 +267,15 @@ bq_status summarize(bq_ctx* c, const std::vector<bq_solve_stats>& st) {
   return w;
 }
 
-void record(bq_ctx* c, std::vector<bq_solve_stats>& st, int b0, int nb, bool fwd) {
+// extra_apps: G applications outside the solver loop (initial residual,
+// adjoint right-hand side, Born prediction)
+void record(bq_ctx* c, std::vector<bq_solve_stats>& st, int b0, int nb, bool fwd, int extra_apps) {
   for (int b = 0; b < nb; ++b) {
     const SysState& s = c->hstate[b];
     bq_solve_stats& o = st[b0 + b];
     if (fwd) { o.iters_fwd = s.iters; o.status_fwd = status_code(s.status); o.relres_fwd = s.res; }
     else { o.iters_adj = s.iters; o.status_adj = status_code(s.status); o.relres_adj = s.res; }
+    o.green_apps += extra_apps + s.mvs;
   }
 }
 
@@ -302,16 +313,18 @@ bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out,
     const int nb = plain ? 1 : B;
     if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
     void* u = want_fields ? (void*)((C<T>*)out + (size_t)b0 * c->V) : c->f[F_U];
+    int extra = c->g.model == BQ_MODEL_BORN ? 0 : 1;
     if (c->g.model == BQ_MODEL_BORN && !want_fields) {
       PassArgs<T> a = pass_args<T>(c, nb, c->inc);
       a.xpot = (const T*)x;
       a.zf_mode = ZF_XUIN;
       a.zi_mode = ZI_G;
       a.out = (C<T>*)c->f[F_V];
-      if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+      if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
       detector<T>(nb, N, (const C<T>*)c->f[F_V], 0, c->inc, nullptr, (C<T>*)out + (size_t)b0 * N2,
                   nullptr, c->np_det, c->stream);
       for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
+      extra = 1;
     } else {
       if (bq_status s = forward_fields<T>(c, (const T*)x, nb, u, plain)) return s;
       if (!want_fields)
@@ -320,7 +333,8 @@ bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out,
     }
     if (bq_status s = check_launch(c, "forward")) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    record(c, stats, b0, nb, true);
+    c->timer.collect();
+    record(c, stats, b0, nb, true, extra);
     for (int b = 0; b < nb; ++b) { stats[b0 + b].status_adj = 0; }
   }
   if (st) std::memcpy(st, stats.data(), B * sizeof(bq_solve_stats));
@@ -353,7 +367,7 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
       a.zf_mode = ZF_XUIN;
       a.zi_mode = ZI_G;
       a.out = (C<T>*)c->f[F_V];
-      if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+      if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
       field = (const C<T>*)c->f[F_V];
       sub = 0;
       for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
@@ -362,7 +376,7 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
       field = (const C<T>*)c->f[F_U];
       sub = 1;
     }
-    record(c, stats, b0, nb, true);
+    record(c, stats, b0, nb, true, 1);
     detector<T>(nb, N, field, sub, c->inc, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det,
                 c->np_det, c->stream);
     // adjoint right-hand side (conjugated): G S^T conj(r)
@@ -372,14 +386,14 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
       a.zf_mode = ZF_DETCONJ;
       a.zi_mode = ZI_G;
       a.out = (C<T>*)c->f[F_W];
-      if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+      if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
     }
     if (born) {
       for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
     } else {
       if (bq_status s = bicgstab<T>(c, nb, (const T*)x, c->f[F_W], c->inc, false, plain)) return s;
     }
-    record(c, stats, b0, nb, false);
+    record(c, stats, b0, nb, false, born ? 1 : 2);
     gradient<T>(nb, N, born ? nullptr : (const C<T>*)c->f[F_U], c->inc, (const C<T>*)c->f[F_W], scale,
                 b0 > 0 ? 1 : 0, (T*)g, c->stream);
     if (bq_status s = check_launch(c, "grad")) return s;
@@ -387,6 +401,7 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
     HIPCHK(c, hipMemcpyAsync(hpart.data(), c->part_det, hpart.size() * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->timer.collect();
     for (double v : hpart) total_loss += v;
   }
   if (loss) *loss = scale * total_loss;
@@ -405,9 +420,10 @@ bq_status do_green(bq_ctx* c, const void* v, void* out, int B, int adjoint) {
   a.zi_mode = adjoint ? ZI_GCONJ : ZI_G;
   a.out = (C<T>*)out;
   a.state = nullptr;
-  if (green_apply<T>(a, c->stream)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+  if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
   if (bq_status s = check_launch(c, "green_apply")) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->timer.collect();
   return BQ_OK;
 }
 
@@ -512,6 +528,22 @@ bq_status bq_green_apply(bq_ctx* c, const void* v, void* out, int B, int adjoint
   if (!c) return BQ_EINVAL;
   return c->g.precision == BQ_F32 ? do_green<float>(c, v, out, B, adjoint)
                                   : do_green<double>(c, v, out, B, adjoint);
+}
+
+bq_status bq_timing(bq_ctx* c, int enable) {
+  if (!c) return BQ_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  c->timer.collect();
+  if (enable) c->timer.reset();
+  c->timer.on = enable != 0;
+  return BQ_OK;
+}
+
+bq_status bq_timing_get(const bq_ctx* c, int pass, double* total_ms, long long* launches) {
+  if (!c || pass < 0 || pass >= P_COUNT) return BQ_EINVAL;
+  if (total_ms) *total_ms = c->timer.total_ms[pass];
+  if (launches) *launches = c->timer.count[pass];
+  return BQ_OK;
 }
 
 }  // extern "C"

@@ -13,8 +13,57 @@ namespace bq {
 inline double cospi_host(double a) { return (double)cosl(3.14159265358979323846264338327950288L * (long double)a); }
 inline double sinpi_host(double a) { return (double)sinl(3.14159265358979323846264338327950288L * (long double)a); }
 
+// ---- device timing of passes (HIP events on the launch stream) -------------
+enum PassId { P_ZF = 0, P_XF, P_YC, P_XI, P_ZI, P_XY, P_VEC, P_COUNT };
+
+struct PassTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<std::pair<int, size_t>> rec;  // (pass, index of the start event)
+  size_t next = 0;
+  double total_ms[P_COUNT] = {};
+  long long count[P_COUNT] = {};
+  int open_pass = -1;
+
+  void start(int pass, hipStream_t s) {
+    if (!on) return;
+    while (ev.size() < next + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+      ev.push_back(e);
+    }
+    (void)hipEventRecord(ev[next], s);
+    rec.push_back({pass, next});
+    open_pass = pass;
+    next += 2;
+  }
+  void stop(hipStream_t s) {
+    if (!on || open_pass < 0) return;
+    (void)hipEventRecord(ev[rec.back().second + 1], s);
+    open_pass = -1;
+  }
+  // call after the stream has been synchronised
+  void collect() {
+    for (auto& r : rec) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[r.second], ev[r.second + 1]) == hipSuccess) {
+        total_ms[r.first] += ms;
+        count[r.first] += 1;
+      }
+    }
+    rec.clear();
+    next = 0;
+  }
+  void reset() {
+    for (int i = 0; i < P_COUNT; ++i) { total_ms[i] = 0.0; count[i] = 0; }
+    rec.clear();
+    next = 0;
+  }
+  ~PassTimer() { for (auto e : ev) (void)hipEventDestroy(e); }
+};
+
 // ---- Green's operator ----------------------------------------------------
-template <typename T> int green_apply(const PassArgs<T>& a, hipStream_t st);
+template <typename T> int green_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm = nullptr);
 template <typename T> int green_num_partials(int N);
 template <typename T> int ghat_precompute(int N, double h, double kb, C<T>* out, hipStream_t st);
 int ghat_oversampling(int N);

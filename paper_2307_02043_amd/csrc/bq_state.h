@@ -28,7 +28,7 @@ struct SysState {
   int first;                    // no iteration done yet
   double tol;
   int max_iter;
-  int pad_;
+  int mvs;                      // solver matvecs done (G applications)
 };
 
 // Which systems a solver pass works on.

@@ -355,14 +355,20 @@ __global__ void __launch_bounds__(NT) k_zi(PassArgs<T> a) {
 }
 
 template <typename T, int N>
-static void launch_split_N(const PassArgs<T>& a, hipStream_t st) {
+static void launch_split_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
   constexpr int TX = tile_w<T>(N);
   const dim3 blk(NT);
+  if (tm) tm->start(P_ZF, st);
   hipLaunchKernelGGL((k_zf<T, N>), dim3(N / TX, N, a.B), blk, 0, st, a);
+  if (tm) { tm->stop(st); tm->start(P_XF, st); }
   hipLaunchKernelGGL((k_xf<T, N>), dim3(2 * N * N / TX, 1, a.B), blk, 0, st, a);
+  if (tm) { tm->stop(st); tm->start(P_YC, st); }
   hipLaunchKernelGGL((k_yc<T, N>), dim3(N / TX, N, 4 * a.B), blk, 0, st, a);
+  if (tm) { tm->stop(st); tm->start(P_XI, st); }
   hipLaunchKernelGGL((k_xi<T, N>), dim3(2 * N * N / TX, 1, a.B), blk, 0, st, a);
+  if (tm) { tm->stop(st); tm->start(P_ZI, st); }
   hipLaunchKernelGGL((k_zi<T, N>), dim3(N / TX, N, a.B), blk, 0, st, a);
+  if (tm) tm->stop(st);
 }
 
 template <typename T>
@@ -376,9 +382,9 @@ int green_num_partials(int N) {
 }
 
 template <typename T>
-int green_apply(const PassArgs<T>& a, hipStream_t st) {
+int green_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
   switch (a.N) {
-#define BQ_CASE(n) case n: launch_split_N<T, n>(a, st); break;
+#define BQ_CASE(n) case n: launch_split_N<T, n>(a, st, tm); break;
     BQ_CASE(8) BQ_CASE(12) BQ_CASE(16) BQ_CASE(24) BQ_CASE(32) BQ_CASE(48) BQ_CASE(64) BQ_CASE(96)
     BQ_CASE(128) BQ_CASE(256)
 #undef BQ_CASE
@@ -387,8 +393,8 @@ int green_apply(const PassArgs<T>& a, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-template int green_apply<float>(const PassArgs<float>&, hipStream_t);
-template int green_apply<double>(const PassArgs<double>&, hipStream_t);
+template int green_apply<float>(const PassArgs<float>&, hipStream_t, PassTimer*);
+template int green_apply<double>(const PassArgs<double>&, hipStream_t, PassTimer*);
 template int green_num_partials<float>(int);
 template int green_num_partials<double>(int);
 

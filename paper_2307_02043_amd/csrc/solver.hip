@@ -274,6 +274,7 @@ __global__ void __launch_bounds__(256) k_sc_alpha(SysState* st, const double* pa
   if (threadIdx.x != 0) return;
   SysState s = st[b];
   s.first = 0;
+  s.mvs += 1;  // the matvec A p of this iteration ran for this system
   const double d = v[0] * v[0] + v[1] * v[1];
   if (!(isfinite(v[0]) && isfinite(v[1]))) {
     s.status = SYS_NONFINITE;
@@ -315,6 +316,7 @@ __global__ void __launch_bounds__(256) k_sc_omega(SysState* st, const double* pa
   sum_partials<3>(part, np, b, v, scratch);
   if (threadIdx.x != 0) return;
   SysState s = st[b];
+  s.mvs += 1;  // the matvec A s of this iteration ran for this system
   if (!finite3(v[0], v[1], v[2])) {
     s.status = SYS_NONFINITE;
   } else {
