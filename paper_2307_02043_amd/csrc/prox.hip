@@ -1,9 +1,483 @@
-// placeholder: weighted TV proximal mapping (filled in below)
+// Weighted proximal mapping of constrained TV on gfx950:
+//   x = argmin_{x in C} 1/2 ||x - v||^2_B + lambda TV(x),  B = tau I + u u^T
+// by the accelerated projected gradient iteration on the dual (Section 4.1,
+// Lemma 4.1 step tau / (4 D lambda)), the Woodbury inverse of B (Section
+// 4.3) and the projection onto the nonnegative orthant of Theorem 3.1,
+// whose scalar root is found by a safeguarded semi-smooth Newton iteration
+// (Algorithm 4.3) that stops exactly once the active set repeats.
+//
+// Variables per dual iteration (V = voxels):
+//   d  = sum_a (D^a)^T R_a                       (divergence of the momentum)
+//   a  = v - (lambda / tau) d                    (stored, the only V temp)
+//   w  = v - lambda B^-1 d = a + kappa u,  kappa = lambda (u.d) / (tau^2 M),
+//        M = 1 + u.u / tau
+//   x  = max(w - u beta / tau, 0) = max(a - u theta, 0),  theta = beta/tau - kappa
+//   psi(theta) = phi(beta) = u.a + kappa u.u - sum_{A} u_n (a_n - u_n theta)
+//                + tau (theta + kappa),  A = {a_n - u_n theta > 0}
+// so on the active set A, psi is linear: psi = K0 + theta (S_A + tau) with
+// K0 = u.a + kappa u.u - T_A + tau kappa, S_A = sum_A u^2, T_A = sum_A u a.
+//
+// Kernels: k_div (a, and FP64 partials of u.d, u.a, S_A, T_A at the warm
+// start theta), k_ssn (partials S_A, T_A at the current theta), k_dual
+// (x at the voxel and its three forward neighbours, P = Proj(R + sigma D x),
+// momentum), k_out.  One-workgroup scalar kernels reduce the partials in a
+// fixed order and run the Newton / bisection logic on the device.
+#include <cmath>
+#include <string>
+#include <vector>
+
 #include "../../include/bq.h"
-extern "C" {
-struct bq_prox { int dummy; };
-bq_status bq_prox_create(int, int, int, int, void*, bq_prox** out) { if (out) *out = nullptr; return BQ_EUNSUPPORTED; }
-bq_status bq_prox_destroy(bq_prox*) { return BQ_OK; }
-const char* bq_prox_last_error(const bq_prox*) { return "not built"; }
-bq_status bq_wprox(bq_prox*, const void*, double, const void*, double, int, int, int, void*, void*, bq_prox_stats*) { return BQ_EUNSUPPORTED; }
+#include "bq_common.h"
+
+namespace bq {
+
+constexpr int PX_WG = 256;
+
+struct ProxState {
+  double tau, lam;
+  double unorm2, M;
+  double kappa;
+  double ua;          // u . a
+  double theta;       // current / final theta
+  double lo, hi;      // bracket of the root in theta
+  double K0, slope;   // line of the last evaluated piece
+  double psi, psi_scale;
+  int done;           // root found for this dual iteration
+  int passes;         // evaluations in this dual iteration
+  int total_passes;
+  int max_passes_seen;
+  int has_u, nonneg;
+  int gaveup;         // dual iterations whose root was not pinned down
+  int pad_;
+  double eps;         // unit roundoff of the image precision
+};
+
+template <typename T>
+struct ProxArgs {
+  int nz, ny, nx;
+  size_t V;
+  const T* v;
+  const T* u;       // may be null
+  T* a;             // V
+  T* P;             // 3V (P_{k-1} in, P_k out)
+  T* R;             // 3V (R_k in, R_{k+1} out)
+  T* x_out;
+  double* partial;  // NP x 4
+  ProxState* st;
+  double sigma;     // dual step
+  double mom;       // (t_k - 1) / t_{k+1}
+  int iso;
+};
+
+__device__ inline void px_coords(size_t i, int ny, int nx, int& z, int& y, int& x) {
+  x = (int)(i % nx);
+  const size_t r = i / nx;
+  y = (int)(r % ny);
+  z = (int)(r / ny);
 }
+
+template <typename T>
+__device__ inline T xval(const ProxArgs<T>& a, size_t i, T theta, bool nonneg, bool has_u) {
+  const T av = a.a[i];
+  const T w = has_u ? av - a.u[i] * theta : av;
+  return nonneg ? (w > T(0) ? w : T(0)) : w;
+}
+
+// a = v - (lambda / tau) d(R); partials: u.d, u.a, S_A(theta0), T_A(theta0)
+template <typename T>
+__global__ void __launch_bounds__(PX_WG) k_div(ProxArgs<T> p) {
+  __shared__ double scratch[(PX_WG / 64) * 4];
+  const ProxState s = *p.st;
+  const double lt = s.lam / s.tau;
+  const T theta0 = (T)s.theta;
+  const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < V; i += (size_t)gridDim.x * PX_WG) {
+    int z, y, x;
+    px_coords(i, p.ny, p.nx, z, y, x);
+    const T* Rz = p.R;
+    const T* Ry = p.R + V;
+    const T* Rx = p.R + 2 * V;
+    T d = 0;
+    // (D^a)^T q at i: q[i - e_a] (if i_a > 0) - q[i] (if i_a < n_a - 1)
+    if (z > 0) d += Rz[i - sz];
+    if (z < p.nz - 1) d -= Rz[i];
+    if (y > 0) d += Ry[i - sy];
+    if (y < p.ny - 1) d -= Ry[i];
+    if (x > 0) d += Rx[i - 1];
+    if (x < p.nx - 1) d -= Rx[i];
+    const T av = p.v[i] - (T)lt * d;
+    p.a[i] = av;
+    if (s.has_u) {
+      const T uv = p.u[i];
+      acc[0] += (double)uv * d;
+      acc[1] += (double)uv * av;
+      if (av - uv * theta0 > T(0)) {
+        acc[2] += (double)uv * uv;
+        acc[3] += (double)uv * av;
+      }
+    }
+  }
+  if (!s.has_u) return;
+  block_sum<PX_WG, 4>(acc, scratch);
+  if (threadIdx.x == 0) {
+    double* q = p.partial + (size_t)blockIdx.x * 4;
+    q[0] = acc[0]; q[1] = acc[1]; q[2] = acc[2]; q[3] = acc[3];
+  }
+}
+
+// partials S_A, T_A at the current theta
+template <typename T>
+__global__ void __launch_bounds__(PX_WG) k_ssn(ProxArgs<T> p) {
+  __shared__ double scratch[(PX_WG / 64) * 2];
+  if (p.st->done) return;
+  const T theta = (T)p.st->theta;
+  double acc[2] = {0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < p.V; i += (size_t)gridDim.x * PX_WG) {
+    const T av = p.a[i], uv = p.u[i];
+    if (av - uv * theta > T(0)) {
+      acc[0] += (double)uv * uv;
+      acc[1] += (double)uv * av;
+    }
+  }
+  block_sum<PX_WG, 2>(acc, scratch);
+  if (threadIdx.x == 0) {
+    double* q = p.partial + (size_t)blockIdx.x * 4;
+    q[2] = acc[0];
+    q[3] = acc[1];
+  }
+}
+
+template <int K0_, int K1_>
+__device__ inline void px_sum(const double* part, int np, double* out, double* scratch) {
+  constexpr int K = K1_ - K0_;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += part[(size_t)i * 4 + K0_ + k];
+  }
+  block_sum<256, K>(v, scratch);
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = v[k];
+}
+
+// Evaluate psi on the piece just measured, update the bracket, decide.
+__device__ inline void px_step(ProxState& s, double SA, double TA, int max_passes) {
+  const double th = s.theta;
+  s.K0 = s.ua + s.kappa * s.unorm2 - TA + s.tau * s.kappa;
+  s.slope = SA + s.tau;
+  s.psi = s.K0 + th * s.slope;
+  s.psi_scale = fabs(s.ua) + fabs(s.kappa) * s.unorm2 + fabs(TA) + fabs(th) * s.slope + s.tau * fabs(s.kappa);
+  s.passes += 1;
+  s.total_passes += 1;
+  if (s.passes > s.max_passes_seen) s.max_passes_seen = s.passes;
+  if (s.psi <= 0.0 && th > s.lo) s.lo = th;
+  if (s.psi >= 0.0 && th < s.hi) s.hi = th;
+  const double newton = -s.K0 / s.slope;  // root of this piece's line
+  const double tol_t = 4.0 * s.eps * fmax(1.0, fabs(th));
+  if (s.psi == 0.0 || fabs(newton - th) <= tol_t || s.hi - s.lo <= tol_t ||
+      fabs(s.psi) <= 16.0 * 2.220446049250313e-16 * s.psi_scale) {
+    // on the root's piece the Newton point is the exact root
+    if (newton >= s.lo && newton <= s.hi) s.theta = newton;
+    s.done = 1;
+    return;
+  }
+  if (s.passes >= max_passes) {  // give up: best bracket point
+    s.theta = (s.lo > -INFINITY && s.hi < INFINITY) ? 0.5 * (s.lo + s.hi) : th;
+    s.done = 1;
+    s.gaveup += 1;
+    return;
+  }
+  double next = newton;
+  if (!(next > s.lo && next < s.hi)) {
+    if (s.lo > -INFINITY && s.hi < INFINITY) next = 0.5 * (s.lo + s.hi);
+    else if (s.lo > -INFINITY) next = s.lo + 2.0 * fabs(s.psi) / s.tau;  // slope >= tau
+    else next = s.hi - 2.0 * fabs(s.psi) / s.tau;
+  }
+  s.theta = next;
+}
+
+__global__ void __launch_bounds__(256) k_px_after_div(ProxState* st, const double* part, int np, int max_passes) {
+  __shared__ double scratch[4 * 4];
+  if (!st->has_u) {
+    if (threadIdx.x == 0) st->done = 1;
+    return;
+  }
+  double v[4];
+  px_sum<0, 4>(part, np, v, scratch);
+  if (threadIdx.x != 0) return;
+  ProxState s = *st;
+  s.kappa = s.lam * v[0] / (s.tau * s.tau * s.M);
+  s.ua = v[1];
+  s.lo = -INFINITY;
+  s.hi = INFINITY;
+  s.passes = 0;
+  s.done = 0;
+  if (!s.nonneg) {  // no constraint: x = w = a + kappa u, i.e. theta = -kappa
+    s.theta = -s.kappa;
+    s.done = 1;
+  } else {
+    px_step(s, v[2], v[3], max_passes);
+  }
+  *st = s;
+}
+
+__global__ void __launch_bounds__(256) k_px_after_ssn(ProxState* st, const double* part, int np, int max_passes) {
+  __shared__ double scratch[4 * 2];
+  if (st->done) return;
+  double v[2];
+  px_sum<2, 4>(part, np, v, scratch);
+  if (threadIdx.x != 0) return;
+  ProxState s = *st;
+  px_step(s, v[0], v[1], max_passes);
+  *st = s;
+}
+
+__global__ void __launch_bounds__(256) k_px_unorm(ProxState* st, const double* part, int np) {
+  __shared__ double scratch[4];
+  double v[1];
+  px_sum<0, 1>(part, np, v, scratch);
+  if (threadIdx.x != 0) return;
+  st->unorm2 = v[0];
+  st->M = 1.0 + v[0] / st->tau;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(PX_WG) k_unorm(ProxArgs<T> p) {
+  __shared__ double scratch[(PX_WG / 64)];
+  double acc[1] = {0.0};
+  for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < p.V; i += (size_t)gridDim.x * PX_WG)
+    acc[0] += (double)p.u[i] * p.u[i];
+  block_sum<PX_WG, 1>(acc, scratch);
+  if (threadIdx.x == 0) p.partial[(size_t)blockIdx.x * 4] = acc[0];
+}
+
+// P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1})
+template <typename T>
+__global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
+  const ProxState* stp = p.st;
+  const bool nonneg = stp->nonneg, has_u = stp->has_u;
+  const T theta = (T)stp->theta;
+  const T sig = (T)p.sigma, mom = (T)p.mom;
+  const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
+  for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < V; i += (size_t)gridDim.x * PX_WG) {
+    int z, y, x;
+    px_coords(i, p.ny, p.nx, z, y, x);
+    const T xc = xval(p, i, theta, nonneg, has_u);
+    const T gz = (z < p.nz - 1) ? xval(p, i + sz, theta, nonneg, has_u) - xc : T(0);
+    const T gy = (y < p.ny - 1) ? xval(p, i + sy, theta, nonneg, has_u) - xc : T(0);
+    const T gx = (x < p.nx - 1) ? xval(p, i + 1, theta, nonneg, has_u) - xc : T(0);
+    T qz = p.R[i] + sig * gz;
+    T qy = p.R[V + i] + sig * gy;
+    T qx = p.R[2 * V + i] + sig * gx;
+    if (p.iso) {
+      const T n = sqrt(qz * qz + qy * qy + qx * qx);
+      if (n > T(1)) {
+        const T inv = T(1) / n;
+        qz *= inv; qy *= inv; qx *= inv;
+      }
+    } else {
+      qz = fmin(fmax(qz, T(-1)), T(1));
+      qy = fmin(fmax(qy, T(-1)), T(1));
+      qx = fmin(fmax(qx, T(-1)), T(1));
+    }
+    const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
+    p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
+    p.R[i] = qz + mom * (qz - oz);
+    p.R[V + i] = qy + mom * (qy - oy);
+    p.R[2 * V + i] = qx + mom * (qx - ox);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(PX_WG) k_out(ProxArgs<T> p) {
+  const bool nonneg = p.st->nonneg, has_u = p.st->has_u;
+  const T theta = (T)p.st->theta;
+  for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < p.V; i += (size_t)gridDim.x * PX_WG)
+    p.x_out[i] = xval(p, i, theta, nonneg, has_u);
+}
+
+template <typename T>
+__global__ void k_fill(T* d, size_t n, T val) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    d[i] = val;
+}
+
+__global__ void k_px_init(ProxState* st, double tau, double lam, int has_u, int nonneg, double eps) {
+  if (threadIdx.x != 0) return;
+  ProxState s{};
+  s.eps = eps;
+  s.tau = tau;
+  s.lam = lam;
+  s.M = 1.0;
+  s.has_u = has_u;
+  s.nonneg = nonneg;
+  s.theta = 0.0;
+  s.done = 1;
+  *st = s;
+}
+
+}  // namespace bq
+
+using namespace bq;
+
+struct bq_prox {
+  int nz = 0, ny = 0, nx = 0, prec = 0;
+  size_t V = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* a = nullptr;
+  void* P = nullptr;
+  void* R = nullptr;
+  double* partial = nullptr;
+  ProxState* st = nullptr;
+  int np = 0;
+  int max_passes = 8;  // evaluations of phi per dual iteration (1 fused + 7 passes)
+};
+
+namespace {
+
+thread_local std::string g_prox_create_error;
+
+int px_grid(size_t V) {
+  size_t g = (V + PX_WG * 4 - 1) / (PX_WG * 4);
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <typename T>
+bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
+                    int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
+  const size_t V = p->V;
+  const hipStream_t s = p->stream;
+  const dim3 g(p->np), b(PX_WG);
+  ProxArgs<T> a{};
+  a.nz = p->nz; a.ny = p->ny; a.nx = p->nx; a.V = V;
+  a.v = (const T*)v;
+  a.u = (const T*)u;
+  a.a = (T*)p->a;
+  a.P = P_io ? (T*)P_io : (T*)p->P;
+  a.R = (T*)p->R;
+  a.x_out = (T*)x_out;
+  a.partial = p->partial;
+  a.st = p->st;
+  a.iso = (tv == BQ_TV_ISO);
+  a.sigma = tau / (4.0 * 3.0 * lam);  // 1 / Lipschitz (Lemma 4.1, omega_min = tau, D = 3), x 2 lambda
+  const int has_u = u != nullptr, nonneg = (cset == BQ_SET_NONNEG);
+  const double eps = sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+  hipLaunchKernelGGL(k_px_init, dim3(1), dim3(64), 0, s, p->st, tau, lam, has_u, nonneg, eps);
+  if (has_u) {
+    hipLaunchKernelGGL((k_unorm<T>), g, b, 0, s, a);
+    hipLaunchKernelGGL(k_px_unorm, dim3(1), dim3(256), 0, s, p->st, (const double*)p->partial, p->np);
+  }
+  // P_0 (given or zero); R_1 = P_0
+  if (!P_io) hipLaunchKernelGGL((k_fill<T>), dim3(1024), dim3(256), 0, s, a.P, 3 * V, T(0));
+  if (hipMemcpyAsync(a.R, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    p->err = "copy of the starting dual point failed";
+    return BQ_EDEVICE;
+  }
+  const int max_launch = (has_u && nonneg) ? p->max_passes - 1 : 0;  // SSN passes per dual iteration
+  double t = 1.0;
+  for (int k = 0; k <= n_iter; ++k) {
+    const bool last = (k == n_iter);
+    if (last) {  // x(P_K): divergence of P_K itself
+      if (hipMemcpyAsync(a.R, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        p->err = "copy failed";
+        return BQ_EDEVICE;
+      }
+    }
+    hipLaunchKernelGGL((k_div<T>), g, b, 0, s, a);
+    hipLaunchKernelGGL(k_px_after_div, dim3(1), dim3(256), 0, s, p->st, (const double*)p->partial, p->np,
+                       p->max_passes);
+    for (int j = 0; j < max_launch; ++j) {
+      hipLaunchKernelGGL((k_ssn<T>), g, b, 0, s, a);
+      hipLaunchKernelGGL(k_px_after_ssn, dim3(1), dim3(256), 0, s, p->st, (const double*)p->partial, p->np,
+                         p->max_passes);
+    }
+    if (last) break;
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    a.mom = (t - 1.0) / tn;
+    t = tn;
+    hipLaunchKernelGGL((k_dual<T>), g, b, 0, s, a);
+  }
+  hipLaunchKernelGGL((k_out<T>), g, b, 0, s, a);
+  if (hipGetLastError() != hipSuccess) {
+    p->err = "kernel launch failed";
+    return BQ_EDEVICE;
+  }
+  ProxState hs{};
+  if (hipMemcpyAsync(&hs, p->st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    p->err = "device error in the proximal mapping";
+    return BQ_EDEVICE;
+  }
+  if (stats) {
+    stats->newton_total = hs.total_passes;
+    stats->newton_max = hs.max_passes_seen;
+    stats->beta_last = hs.tau * (hs.theta + hs.kappa);
+    stats->phi_last = fabs(hs.psi);
+  }
+  if (hs.gaveup > 0) {
+    p->err = "semi-smooth Newton hit its pass limit in " + std::to_string(hs.gaveup) + " dual iterations";
+    return BQ_NOTCONV;
+  }
+  return BQ_OK;
+}
+
+void free_prox(bq_prox* p) {
+  if (!p) return;
+  void* ptrs[] = {p->a, p->P, p->R, p->partial, p->st};
+  for (void* q : ptrs) if (q) (void)hipFree(q);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+bq_status bq_prox_create(int nz, int ny, int nx, int precision, void* stream, bq_prox** out) {
+  if (!out) { g_prox_create_error = "out is NULL"; return BQ_EINVAL; }
+  *out = nullptr;
+  if (nz < 2 || ny < 2 || nx < 2) { g_prox_create_error = "each image dimension must be >= 2"; return BQ_EINVAL; }
+  if (precision != BQ_F32 && precision != BQ_F64) { g_prox_create_error = "precision"; return BQ_EINVAL; }
+  bq_prox* p = new bq_prox();
+  p->nz = nz; p->ny = ny; p->nx = nx; p->prec = precision;
+  p->V = (size_t)nz * ny * nx;
+  p->stream = (hipStream_t)stream;
+  p->np = px_grid(p->V);
+  const size_t es = precision == BQ_F32 ? 4 : 8;
+  if (hipMalloc(&p->a, p->V * es) != hipSuccess || hipMalloc(&p->P, 3 * p->V * es) != hipSuccess ||
+      hipMalloc(&p->R, 3 * p->V * es) != hipSuccess ||
+      hipMalloc((void**)&p->partial, (size_t)p->np * 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->st, sizeof(ProxState)) != hipSuccess) {
+    free_prox(p);
+    g_prox_create_error = "out of device memory";
+    return BQ_ENOMEM;
+  }
+  *out = p;
+  return BQ_OK;
+}
+
+bq_status bq_prox_destroy(bq_prox* p) {
+  if (p) (void)hipStreamSynchronize(p->stream);
+  free_prox(p);
+  return BQ_OK;
+}
+
+const char* bq_prox_last_error(const bq_prox* p) { return p ? p->err.c_str() : g_prox_create_error.c_str(); }
+
+bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* u, double lambda, int tv, int cset,
+                   int n_iter, void* x_out, void* P_io, bq_prox_stats* st) {
+  if (!p) return BQ_EINVAL;
+  if (!v || !x_out) { p->err = "null device pointer"; return BQ_EINVAL; }
+  if (!(tau > 0) || !(lambda > 0) || n_iter < 0) { p->err = "tau, lambda must be > 0 and n_iter >= 0"; return BQ_EINVAL; }
+  if (tv != BQ_TV_ISO && tv != BQ_TV_ANISO) { p->err = "tv"; return BQ_EINVAL; }
+  if (cset != BQ_SET_NONE && cset != BQ_SET_NONNEG) { p->err = "cset"; return BQ_EINVAL; }
+  return p->prec == BQ_F32 ? run_wprox<float>(p, v, tau, u, lambda, tv, cset, n_iter, x_out, P_io, st)
+                           : run_wprox<double>(p, v, tau, u, lambda, tv, cset, n_iter, x_out, P_io, st);
+}
+
+}  // extern "C"

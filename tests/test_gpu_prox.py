@@ -1,0 +1,119 @@
+"""GPU parity of the weighted TV proximal mapping against the CPU oracle.
+
+Same number of dual iterations on both sides; the oracle finds Theorem 3.1's
+root exactly by sorting breakpoints, the GPU by safeguarded semi-smooth
+Newton.  Tolerances (relative l2 on x): 1e-10 FP64, 2e-4 FP32.
+"""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import tvprox as tp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _inputs(shape, seed):
+    rng = np.random.default_rng(seed)
+    v = 0.02 * rng.random(shape) + 0.005 * rng.standard_normal(shape)
+    u = 0.1 * rng.standard_normal(shape)
+    return v, u
+
+
+def _run(dev, shape, prec, v, tau, u, lam, tv, cset, n_iter, P=None):
+    from paper_2307_02043_amd import WProx
+    rd = torch.float64 if prec == "f64" else torch.float32
+    px = WProx(shape, prec)
+    Pt = None if P is None else torch.from_numpy(np.ascontiguousarray(P)).to(dev, rd)
+    x, info = px(torch.from_numpy(v).to(dev, rd), tau,
+                 None if u is None else torch.from_numpy(u).to(dev, rd),
+                 lam, tv, cset, n_iter, P=Pt)
+    out = x.cpu().numpy().astype(np.float64), info, (None if Pt is None else Pt.cpu().numpy())
+    px.close()
+    return out
+
+
+@pytest.mark.parametrize("shape", [(13, 17, 19), (16, 16, 16)])
+@pytest.mark.parametrize("tv", ["iso", "aniso"])
+@pytest.mark.parametrize("cset", ["nonneg", "none"])
+@pytest.mark.parametrize("rank", [1, 0])
+def test_wprox_f64_matches_oracle(dev, shape, tv, cset, rank):
+    v, u = _inputs(shape, sum(shape) + rank)
+    u = u if rank else None
+    ref = tp.wprox(v, 0.8, u, 2e-3, tv, cset, n_iter=30)
+    got, info, _ = _run(dev, shape, "f64", v, 0.8, u, 2e-3, tv, cset, 30)
+    assert _rel(got, ref) < 1e-10, _rel(got, ref)
+    if cset == "nonneg":
+        assert np.all(got >= 0)
+    if rank and cset == "nonneg":
+        assert info.newton_max <= 8 and info.newton_total >= 31
+
+
+@pytest.mark.parametrize("tv", ["iso", "aniso"])
+def test_wprox_f32_matches_oracle(dev, tv):
+    shape = (20, 24, 28)
+    v, u = _inputs(shape, 77)
+    ref = tp.wprox(v, 1.0, u, 1e-3, tv, "nonneg", n_iter=40)
+    got, info, _ = _run(dev, shape, "f32", v, 1.0, u, 1e-3, tv, "nonneg", 40)
+    assert _rel(got, ref) < 2e-4, _rel(got, ref)
+
+
+def test_wprox_c1_workload(dev):
+    """32^3 isotropic prox of the first workload: lambda 1e-3, 50 iterations,
+    nonnegativity, metric tau I + u u^T."""
+    w = syn.WORKLOADS["c1_ls32_f64"]
+    v, tau, u = syn.prox_inputs(w)
+    ref = tp.wprox(v, tau, u, w.prox_lambda, "iso", "nonneg", n_iter=w.prox_iters)
+    for prec, tol in (("f64", 1e-10), ("f32", 2e-4)):
+        got, info, _ = _run(dev, v.shape, prec, v, tau, u, w.prox_lambda, "iso", "nonneg", w.prox_iters)
+        assert _rel(got, ref) < tol, (prec, _rel(got, ref))
+
+
+@pytest.mark.slow
+def test_wprox_c2_workload_aniso(dev):
+    """64^3 anisotropic prox, 100 iterations (second workload)."""
+    w = syn.WORKLOADS["c2_born64_f32"]
+    v, tau, u = syn.prox_inputs(w)
+    ref = tp.wprox(v, tau, u, w.prox_lambda, "aniso", "nonneg", n_iter=w.prox_iters)
+    got, info, _ = _run(dev, v.shape, "f32", v, tau, u, w.prox_lambda, "aniso", "nonneg", w.prox_iters)
+    assert _rel(got, ref) < 2e-4
+
+
+def test_wprox_warm_start_and_zero_iterations(dev):
+    shape = (12, 14, 10)
+    v, u = _inputs(shape, 5)
+    # n_iter = 0: x = prox^B_C(v) (Theorem 3.1 projection only)
+    got0, _, _ = _run(dev, shape, "f64", v, 0.5, u, 1e-3, "iso", "nonneg", 0)
+    ref0, _ = tp.weighted_projection_nonneg(v, 0.5, u)
+    assert _rel(got0, ref0) < 1e-12
+    # dual warm start: continue from P_20 for 15 more iterations
+    x20, P20 = tp.wprox(v, 0.5, u, 1e-3, "iso", "nonneg", n_iter=20, return_dual=True)
+    ref = tp.wprox(v, 0.5, u, 1e-3, "iso", "nonneg", n_iter=15, P0=P20)
+    P = np.zeros((3,) + shape)
+    got20, _, Pg = _run(dev, shape, "f64", v, 0.5, u, 1e-3, "iso", "nonneg", 20, P=P)
+    assert _rel(got20, x20) < 1e-10 and _rel(Pg, P20) < 1e-10
+    got, _, _ = _run(dev, shape, "f64", v, 0.5, u, 1e-3, "iso", "nonneg", 15, P=Pg)
+    assert _rel(got, ref) < 1e-10
+
+
+def test_wprox_rejects_bad_arguments(dev):
+    from paper_2307_02043_amd import BQError, WProx
+    px = WProx((8, 8, 8), "f64")
+    v = torch.zeros((8, 8, 8), dtype=torch.float64, device=dev)
+    with pytest.raises(BQError):
+        px(v, -1.0, None, 1e-3)
+    with pytest.raises(BQError):
+        px(v, 1.0, None, 0.0)
+    px.close()
