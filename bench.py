@@ -135,7 +135,10 @@ def main():
     csz = 8  # complex64
     alg_bytes = apps * PASS_UNITS[dom] * V * csz
     achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"k_{dom}<float,{N}>", "achieved": round(achieved, 1),
+    reg = N in (16, 32, 64, 128, 256)  # register-resident z/y passes on power-of-two grids
+    kname = {"yc": "k_yc_r" if reg else "k_yc", "zf": "k_zf_r" if reg else "k_zf",
+             "zi": "k_zi_r" if reg else "k_zi", "xf": "k_xf", "xi": "k_xi", "xy": "k_xy"}[dom]
+    roofline = {"bound": "hbm", "kernel": f"{kname}<float,{N}>", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None,
                 "bytes_per_system_application": PASS_UNITS[dom] * V * csz,

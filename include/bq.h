@@ -61,8 +61,11 @@ typedef enum { BQ_F32 = 0, BQ_F64 = 1 } bq_precision;
 typedef enum { BQ_MODEL_LS = 0, BQ_MODEL_BORN = 1 } bq_model;
 
 /* flags of bq_geom */
-#define BQ_FLAG_PLAIN 1u /* solve one illumination at a time, with a host
-                            round trip per BiCGSTAB iteration (baseline) */
+#define BQ_FLAG_PLAIN 1u    /* solve one illumination at a time, with a host
+                               round trip per BiCGSTAB iteration (baseline) */
+#define BQ_FLAG_FUSED_XY 2u /* run the x/y FFTs of G as one LDS-resident plane
+                               pass where it exists (N = 16..128 complex64,
+                               16..64 complex128) instead of three passes   */
 
 /* Grid, optics and solver settings (Section 6.1 describes the setting). */
 typedef struct {

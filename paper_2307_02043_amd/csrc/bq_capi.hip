@@ -141,6 +141,7 @@ PassArgs<T> pass_args(bq_ctx* c, int B, const C<double>* inc) {
   a.twN = (const C<T>*)c->twN;
   a.twH = (const C<T>*)c->twH;
   a.partial = c->part_mv;
+  a.xy_fused = (c->g.flags & BQ_FLAG_FUSED_XY) ? 1 : 0;
   return a;
 }
 

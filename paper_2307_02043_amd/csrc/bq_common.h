@@ -96,12 +96,42 @@ __device__ inline void dft8(C<T>* v) {
   v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
 }
 
+// 16-point DFT as 4 x 4: n = n1 + 4 n2, k = k2 + 4 k1; inner DFT-4 over n2,
+// twiddle W16^{n1 k2}, outer DFT-4 over n1; natural-order output.
+template <typename T, bool INV>
+__device__ inline void dft16(C<T>* v) {
+  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173),
+          r2 = T(0.70710678118654752440);
+  C<T> a[4][4];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) a[n1][n2] = v[n1 + 4 * n2];
+    dft4<T, INV>(a[n1]);  // a[n1][k2]
+  }
+  // W16^m = (cos(m pi/8), -sin(m pi/8)); conjugated for the inverse
+  const T sg = INV ? T(1) : T(-1);
+  const C<T> w1{c1, sg * s1}, w2{r2, sg * r2}, w3{s1, sg * c1};
+  const C<T> w6{-r2, sg * r2}, w9{-c1, -sg * s1};
+  a[1][1] = cmul(a[1][1], w1); a[1][2] = cmul(a[1][2], w2); a[1][3] = cmul(a[1][3], w3);
+  a[2][1] = cmul(a[2][1], w2); a[2][2] = rot90<T, INV>(a[2][2]); a[2][3] = cmul(a[2][3], w6);
+  a[3][1] = cmul(a[3][1], w3); a[3][2] = cmul(a[3][2], w6); a[3][3] = cmul(a[3][3], w9);
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    C<T> b[4] = {a[0][k2], a[1][k2], a[2][k2], a[3][k2]};
+    dft4<T, INV>(b);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) v[k2 + 4 * k1] = b[k1];
+  }
+}
+
 template <typename T, bool INV, int R>
 __device__ inline void dftR(C<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 3) dft3<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
   else if constexpr (R == 8) dft8<T, INV>(v);
+  else if constexpr (R == 16) dft16<T, INV>(v);
   else static_assert(R == 2, "unsupported radix");
 }
 
@@ -144,7 +174,9 @@ __device__ inline void stockham_stage(C<T>* buf, int ls, int es, const C<T>* tw)
   for (int s = 0; s < BPT; ++s) {
     const int j = tid + s * NTHR;
     if ((NB % NTHR) == 0 || j < NB) {
-      const int line = j / M, jj = j - line * M;
+      // lines vary fastest across lanes: lane-adjacent accesses are a line
+      // stride apart, which the padded stride spreads over the LDS banks
+      const int line = j % NL, jj = j / NL;
       const C<T>* base = buf + line * ls;
       const int k = jj % NS;
 #pragma unroll
@@ -164,7 +196,7 @@ __device__ inline void stockham_stage(C<T>* buf, int ls, int es, const C<T>* tw)
   for (int s = 0; s < BPT; ++s) {
     const int j = tid + s * NTHR;
     if ((NB % NTHR) == 0 || j < NB) {
-      const int line = j / M, jj = j - line * M;
+      const int line = j % NL, jj = j / NL;
       C<T>* base = buf + line * ls;
       const int k = jj % NS;
       const int d = (jj / NS) * NS * R + k;
@@ -191,6 +223,68 @@ struct StockhamRun {
 template <typename T, int LEN, int NL, int NTHR, bool INV>
 __device__ inline void lds_fft(C<T>* buf, int ls, int es, const C<T>* tw) {
   StockhamRun<T, LEN, NL, NTHR, INV, 0, 1>::run(buf, ls, es, tw);
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident line FFT: a line of N = R1 R2 points is held by R2
+// threads with R1 points each (thread j holds x[j + R2 m]).  A radix-R1 DFT
+// in registers, twiddles W_N^{j k1}, one exchange through LDS and radix-R2
+// DFTs give X[k1 + R1 k2] with k1 = j + R2 i held by thread j at
+// d[i R2 + k2].  One LDS write and one read per transform (against two per
+// radix stage for the LDS Stockham routine).  All threads of the workgroup
+// must call it together (it synchronises the workgroup).
+// ---------------------------------------------------------------------------
+// Exchange slot of value (k1, jj): the jj index is XOR-swizzled by k1 so that
+// the R2 lanes of a line never hit the same LDS bank group.
+template <int R2>
+__device__ inline int xslot(int k1, int jj) { return k1 * R2 + (jj ^ (k1 & (R2 - 1))); }
+
+// Forward (or inverse-signed) FFT of one line distributed over R2 threads.
+// In: d[m] = x[j + R2 m].  Out: d[i R2 + k2] = X[k1 + R1 k2], k1 = j + R2 i.
+template <typename T, int N, int R1, int R2, bool INV>
+__device__ inline void line_fft(C<T>* d, C<T>* line, int es, int j, const C<T>* tw) {
+  constexpr int NI = R1 / R2;
+  dftR<T, INV, R1>(d);
+#pragma unroll
+  for (int k1 = 1; k1 < R1; ++k1) {
+    const C<T> w = tw[j * k1];
+    d[k1] = INV ? cmulc(d[k1], w) : cmul(d[k1], w);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) line[xslot<R2>(k1, j) * es] = d[k1];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int k1 = j + R2 * i;
+#pragma unroll
+    for (int jj = 0; jj < R2; ++jj) d[i * R2 + jj] = line[xslot<R2>(k1, jj) * es];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NI; ++i) dftR<T, INV, R2>(&d[i * R2]);
+}
+
+// Inverse of line_fft (unnormalised): from the distributed spectrum back to
+// d[m] = N x[j + R2 m].
+template <typename T, int N, int R1, int R2>
+__device__ inline void line_ifft(C<T>* d, C<T>* line, int es, int j, const C<T>* tw) {
+  constexpr int NI = R1 / R2;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int k1 = j + R2 * i;
+    dftR<T, true, R2>(&d[i * R2]);
+#pragma unroll
+    for (int jj = 0; jj < R2; ++jj) {
+      C<T> v = d[i * R2 + jj];
+      if (jj * k1) v = cmulc(v, tw[jj * k1]);
+      line[xslot<R2>(k1, jj) * es] = v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) d[k1] = line[xslot<R2>(k1, j) * es];
+  __syncthreads();
+  dftR<T, true, R1>(d);
 }
 
 // ---------------------------------------------------------------------------

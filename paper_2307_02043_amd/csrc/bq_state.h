@@ -84,6 +84,7 @@ struct PassArgs {
   C<T>* out;
   C<T>* out2;
   double* partial;             // B x NP x 4
+  int xy_fused;                // use the LDS-resident plane pass when available
 };
 
 }  // namespace bq

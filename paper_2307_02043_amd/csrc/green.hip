@@ -373,6 +373,7 @@ static void launch_split_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) 
 
 template <typename T>
 int green_num_partials(int N) {
+  if (reg_supported<T>(N)) return reg_num_partials(N);
   switch (N) {
 #define BQ_NP(n) case n: return (n / tile_w<T>(n)) * n;
     BQ_NP(8) BQ_NP(12) BQ_NP(16) BQ_NP(24) BQ_NP(32) BQ_NP(48) BQ_NP(64) BQ_NP(96) BQ_NP(128) BQ_NP(256)
@@ -381,8 +382,14 @@ int green_num_partials(int N) {
   }
 }
 
+// Power-of-two grids use the register-resident passes (green_reg.hip); the
+// other supported sizes (factors of 3) use the LDS Stockham passes here.
 template <typename T>
 int green_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
+  if (reg_supported<T>(a.N)) {
+    if (reg_apply<T>(a, st, tm)) return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  }
   switch (a.N) {
 #define BQ_CASE(n) case n: launch_split_N<T, n>(a, st, tm); break;
     BQ_CASE(8) BQ_CASE(12) BQ_CASE(16) BQ_CASE(24) BQ_CASE(32) BQ_CASE(48) BQ_CASE(64) BQ_CASE(96)
@@ -392,6 +399,23 @@ int green_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
+
+template <typename T, int N>
+void launch_xf_stockham(const PassArgs<T>& a, hipStream_t st) {
+  constexpr int TX = tile_w<T>(N);
+  hipLaunchKernelGGL((k_xf<T, N>), dim3(2 * N * N / TX, 1, a.B), dim3(NT), 0, st, a);
+}
+template <typename T, int N>
+void launch_xi_stockham(const PassArgs<T>& a, hipStream_t st) {
+  constexpr int TX = tile_w<T>(N);
+  hipLaunchKernelGGL((k_xi<T, N>), dim3(2 * N * N / TX, 1, a.B), dim3(NT), 0, st, a);
+}
+#define BQ_XI(T, n) \
+  template void launch_xf_stockham<T, n>(const PassArgs<T>&, hipStream_t); \
+  template void launch_xi_stockham<T, n>(const PassArgs<T>&, hipStream_t);
+BQ_XI(float, 16) BQ_XI(float, 32) BQ_XI(float, 64) BQ_XI(float, 128) BQ_XI(float, 256)
+BQ_XI(double, 16) BQ_XI(double, 32) BQ_XI(double, 64) BQ_XI(double, 128) BQ_XI(double, 256)
+#undef BQ_XI
 
 template int green_apply<float>(const PassArgs<float>&, hipStream_t, PassTimer*);
 template int green_apply<double>(const PassArgs<double>&, hipStream_t, PassTimer*);
