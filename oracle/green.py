@@ -93,10 +93,14 @@ def kernel_padded(N: int, h: float, kb: float, Q: int | None = None,
 
     Q = oversampling(N) if Q is None else Q
     R = truncation_radius(N, h)
-    xi = 2.0 * np.pi * np.fft.fftfreq(Q, d=h)
-    s2 = (xi[:, None, None] ** 2 + xi[None, :, None] ** 2) + xi[None, None, :] ** 2
-    gh = ghat_truncated(np.sqrt(s2), kb, R)
-    del s2
+    # |xi|^2 = (2 pi / (Q h))^2 (kx^2 + ky^2 + kz^2) with integer k: the radial
+    # transform is evaluated once per distinct integer k^2 and gathered
+    k = np.fft.fftfreq(Q, d=1.0 / Q).astype(np.int64)
+    k2 = (k[:, None, None] ** 2 + k[None, :, None] ** 2) + k[None, None, :] ** 2
+    dk = 2.0 * np.pi / (Q * h)
+    table = ghat_truncated(dk * np.sqrt(np.arange(int(k2.max()) + 1, dtype=np.float64)), kb, R)
+    gh = table[k2]
+    del k2
     K = sfft.ifftn(gh, workers=workers)
     del gh
     idx = np.r_[np.arange(0, N), np.arange(Q - N, Q)]
