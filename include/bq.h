@@ -144,6 +144,13 @@ bq_status bq_fields(bq_ctx* ctx, const void* x, const int* idx, int B, void* u_o
 bq_status bq_grad(bq_ctx* ctx, const void* x, const void* y, const int* idx, int B, double scale,
                   void* g_out, double* loss, bq_solve_stats* st);
 
+/* Mini-batch loss only: *loss = scale * sum_b 1/2 ||S(u_b - u_in,b) - y_b||^2
+ * (forward solves and detector residual, no adjoint solve).  Arguments as
+ * for bq_grad.  Used by differentiation wrappers whose backward pass calls
+ * bq_grad, which solves the forward fields again instead of storing them. */
+bq_status bq_loss(bq_ctx* ctx, const void* x, const void* y, const int* idx, int B, double scale,
+                  double* loss, bq_solve_stats* st);
+
 /* Apply the discrete Green's operator to B complex fields:
  * out_b = G v_b (adjoint != 0: G^H v_b).  v, out: device, B x N^3 complex;
  * v and out must not overlap. */

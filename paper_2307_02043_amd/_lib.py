@@ -22,7 +22,7 @@ BQ_SET_NONE, BQ_SET_NONNEG = 0, 1
 PASS_NAMES = ("zf", "xf", "yc", "xi", "zi", "xy", "vec")
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
-            "bq_grad", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",
+            "bq_grad", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",
             "bq_prox_last_error", "bq_wprox")
 
 
@@ -68,6 +68,7 @@ def load() -> ct.CDLL:
         "bq_forward": ([P, P, ct.POINTER(I), I, P, ct.POINTER(SolveStats)], I),
         "bq_fields": ([P, P, ct.POINTER(I), I, P, ct.POINTER(SolveStats)], I),
         "bq_grad": ([P, P, P, ct.POINTER(I), I, D, P, ct.POINTER(D), ct.POINTER(SolveStats)], I),
+        "bq_loss": ([P, P, P, ct.POINTER(I), I, D, ct.POINTER(D), ct.POINTER(SolveStats)], I),
         "bq_green_apply": ([P, P, P, I, I], I),
         "bq_timing": ([P, I], I),
         "bq_timing_get": ([P, I, ct.POINTER(D), ct.POINTER(ct.c_longlong)], I),

@@ -147,6 +147,17 @@ class LSContext:
                                           _ptr(g), ct.byref(loss), st))
         return g, loss.value, _stats(st, B, s)
 
+    def loss(self, x: torch.Tensor, y: torch.Tensor, idx, scale: float):
+        N = self.N
+        x = self._real(x, (N, N, N))
+        a, pidx, B = self._idx(idx)
+        y = self._cplx(y, (B, N, N))
+        loss = ct.c_double(0.0)
+        st = (L.SolveStats * B)()
+        s = self._check(self._lib.bq_loss(self._h, _ptr(x), _ptr(y), pidx, B, float(scale),
+                                          ct.byref(loss), st))
+        return loss.value, _stats(st, B, s)
+
     def green(self, v: torch.Tensor, adjoint: bool = False) -> torch.Tensor:
         N = self.N
         if v.dim() == 3:

@@ -342,6 +342,57 @@ bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out,
   return summarize(c, stats);
 }
 
+// Loss only: forward fields, detector residual and its FP64 half squared norm.
+template <typename T>
+bq_status do_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, double* loss,
+                  bq_solve_stats* st) {
+  if (bq_status s = check_batch(c, idx, B)) return s;
+  if (!x || !y || !loss) return set_err(c, BQ_EINVAL, "null pointer");
+  const bool plain = (c->g.flags & BQ_FLAG_PLAIN) != 0;
+  if (bq_status s = ensure_capacity(c, plain ? 1 : B)) return s;
+  std::vector<bq_solve_stats> stats(B);
+  const int N = c->g.N;
+  const size_t N2 = (size_t)N * N;
+  const bool born = c->g.model == BQ_MODEL_BORN;
+  double total = 0.0;
+  std::vector<double> hpart;
+  const int step = plain ? 1 : B;
+  for (int b0 = 0; b0 < B; b0 += step) {
+    const int nb = step;
+    if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
+    const C<T>* field;
+    int sub;
+    if (born) {
+      PassArgs<T> a = pass_args<T>(c, nb, c->inc);
+      a.xpot = (const T*)x;
+      a.zf_mode = ZF_XUIN;
+      a.zi_mode = ZI_G;
+      a.out = (C<T>*)c->f[F_V];
+      if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
+      field = (const C<T>*)c->f[F_V];
+      sub = 0;
+      for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
+    } else {
+      if (bq_status s = bicgstab<T>(c, nb, (const T*)x, c->f[F_U], c->inc, true, plain)) return s;
+      field = (const C<T>*)c->f[F_U];
+      sub = 1;
+    }
+    record(c, stats, b0, nb, true, 1);
+    detector<T>(nb, N, field, sub, c->inc, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det,
+                c->np_det, c->stream);
+    if (bq_status s = check_launch(c, "loss")) return s;
+    hpart.resize((size_t)nb * c->np_det);
+    HIPCHK(c, hipMemcpyAsync(hpart.data(), c->part_det, hpart.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->timer.collect();
+    for (double v : hpart) total += v;
+  }
+  *loss = scale * total;
+  if (st) std::memcpy(st, stats.data(), B * sizeof(bq_solve_stats));
+  return summarize(c, stats);
+}
+
 template <typename T>
 bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, void* g,
                   double* loss, bq_solve_stats* st) {
@@ -523,6 +574,13 @@ bq_status bq_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   if (!c) return BQ_EINVAL;
   return c->g.precision == BQ_F32 ? do_grad<float>(c, x, y, idx, B, scale, g_out, loss, st)
                                   : do_grad<double>(c, x, y, idx, B, scale, g_out, loss, st);
+}
+
+bq_status bq_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, double* loss,
+                  bq_solve_stats* st) {
+  if (!c) return BQ_EINVAL;
+  return c->g.precision == BQ_F32 ? do_loss<float>(c, x, y, idx, B, scale, loss, st)
+                                  : do_loss<double>(c, x, y, idx, B, scale, loss, st);
 }
 
 bq_status bq_green_apply(bq_ctx* c, const void* v, void* out, int B, int adjoint) {
