@@ -62,6 +62,8 @@ def main():
                     help="timed steps of the plain FP64 path (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=10,
                     help="BiCGSTAB iterations of the oracle sample (0: skip)")
+    ap.add_argument("--prox-workload", default="c5_ls256_f32",
+                    help="workload whose weighted prox is timed alongside ('' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -197,6 +199,11 @@ def main():
                           f"3 extra applications of G")}
         log(f"oracle: {t_iter:.2f} s per BiCGSTAB iteration")
 
+    # ---- weighted TV prox (second kernel of the method) ---------------------
+    prox = None
+    if args.prox_workload:
+        prox = bench_prox(syn.WORKLOADS[args.prox_workload], dev)
+
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -222,8 +229,50 @@ def main():
                    "green_apps_per_step": apps / args.steps,
                    "bicgstab_iters_per_s": round(iters / elapsed, 1), "setup_s": round(setup_s, 2)},
         "passes_ms_per_step": {k: round(v / args.steps, 3) for k, v in pass_ms.items()},
+        "prox": prox,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_prox(w, dev, reps=2):
+    """One weighted prox of a workload (its TV kind, metric tau I + u u^T,
+    lambda and iteration count), FP32, inputs resident on the device.
+
+    Algorithmic HBM bytes per dual iteration, in V = N^3 FP32 images: the
+    divergence pass reads R (3), v, u and writes a (6); each root-finding
+    pass reads a, u (2); the dual update reads a, u, R (3), P (3) and writes
+    P, R (6) (14).  Total 20 + 2 n_pass per iteration.
+    """
+    import torch
+
+    import synthetic as syn
+    from paper_2307_02043_amd import WProx
+
+    v, tau, u = syn.prox_inputs(w)
+    V = v.size
+    vt = torch.from_numpy(v).to(dev, torch.float32)
+    ut = torch.from_numpy(u).to(dev, torch.float32)
+    px = WProx(v.shape, "f32")
+    x, info = px(vt, tau, ut, w.prox_lambda, w.prox_tv, "nonneg", w.prox_iters)  # warmup
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        x, info = px(vt, tau, ut, w.prox_lambda, w.prox_tv, "nonneg", w.prox_iters)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / reps
+    K = w.prox_iters
+    extra_passes = info.newton_total - (K + 1)   # evaluations beyond the fused one
+    units = 20.0 * K + 2.0 * extra_passes + 6.0 + 1.0  # + final divergence and output
+    achieved = units * V * 4 / el / 1e9
+    px.close()
+    log(f"prox {w.name}: {el * 1e3:.2f} ms per call, {info.newton_total} root evaluations")
+    return {"workload": (f"{w.name} prox: {w.N}^3 {w.prox_tv}-TV, nonnegativity, metric tau I + u u^T, "
+                         f"lambda {w.prox_lambda:g}, {K} dual iterations, FP32"),
+            "ms_per_call": round(el * 1e3, 3), "dual_iters_per_s": round(K / el, 1),
+            "root_evaluations": info.newton_total, "max_evaluations_per_iter": info.newton_max,
+            "roofline": {"bound": "hbm", "scope": "whole call", "achieved": round(achieved, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "bytes": units * V * 4}}
 
 
 if __name__ == "__main__":

@@ -50,6 +50,7 @@ struct ProxState {
   int gaveup;         // dual iterations whose root was not pinned down
   int pad_;
   double eps;         // unit roundoff of the image precision
+  double t, mom;      // FISTA sequence t_k and the momentum (t_k - 1) / t_{k+1}
 };
 
 template <typename T>
@@ -65,7 +66,6 @@ struct ProxArgs {
   double* partial;  // NP x 4
   ProxState* st;
   double sigma;     // dual step
-  double mom;       // (t_k - 1) / t_{k+1}
   int iso;
 };
 
@@ -202,13 +202,22 @@ __device__ inline void px_step(ProxState& s, double SA, double TA, int max_passe
 __global__ void __launch_bounds__(256) k_px_after_div(ProxState* st, const double* part, int np, int max_passes) {
   __shared__ double scratch[4 * 4];
   if (!st->has_u) {
-    if (threadIdx.x == 0) st->done = 1;
+    if (threadIdx.x == 0) {
+      const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st->t * st->t));
+      st->mom = (st->t - 1.0) / tn;
+      st->t = tn;
+      st->done = 1;
+    }
     return;
   }
   double v[4];
   px_sum<0, 4>(part, np, v, scratch);
   if (threadIdx.x != 0) return;
   ProxState s = *st;
+  // momentum of the dual update that follows this divergence
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * s.t * s.t));
+  s.mom = (s.t - 1.0) / tn;
+  s.t = tn;
   s.kappa = s.lam * v[0] / (s.tau * s.tau * s.M);
   s.ua = v[1];
   s.lo = -INFINITY;
@@ -260,7 +269,7 @@ __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
   const ProxState* stp = p.st;
   const bool nonneg = stp->nonneg, has_u = stp->has_u;
   const T theta = (T)stp->theta;
-  const T sig = (T)p.sigma, mom = (T)p.mom;
+  const T sig = (T)p.sigma, mom = (T)stp->mom;
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
   for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < V; i += (size_t)gridDim.x * PX_WG) {
     int z, y, x;
@@ -316,6 +325,7 @@ __global__ void k_px_init(ProxState* st, double tau, double lam, int has_u, int 
   s.nonneg = nonneg;
   s.theta = 0.0;
   s.done = 1;
+  s.t = 1.0;
   *st = s;
 }
 
@@ -326,7 +336,9 @@ using namespace bq;
 struct bq_prox {
   int nz = 0, ny = 0, nx = 0, prec = 0;
   size_t V = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // caller's stream
+  hipStream_t own = nullptr;     // library stream (capturable), default priority
+  hipEvent_t ev = nullptr;
   std::string err;
   void* a = nullptr;
   void* P = nullptr;
@@ -352,7 +364,12 @@ template <typename T>
 bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
                     int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
   const size_t V = p->V;
-  const hipStream_t s = p->stream;
+  // order after the caller's pending work, then run on the library stream
+  if (hipEventRecord(p->ev, p->stream) != hipSuccess || hipStreamWaitEvent(p->own, p->ev, 0) != hipSuccess) {
+    p->err = "stream synchronisation failed";
+    return BQ_EDEVICE;
+  }
+  const hipStream_t s = p->own;
   const dim3 g(p->np), b(PX_WG);
   ProxArgs<T> a{};
   a.nz = p->nz; a.ny = p->ny; a.nx = p->nx; a.V = V;
@@ -374,21 +391,15 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
     hipLaunchKernelGGL(k_px_unorm, dim3(1), dim3(256), 0, s, p->st, (const double*)p->partial, p->np);
   }
   // P_0 (given or zero); R_1 = P_0
-  if (!P_io) hipLaunchKernelGGL((k_fill<T>), dim3(1024), dim3(256), 0, s, a.P, 3 * V, T(0));
+  if (!P_io) hipLaunchKernelGGL((k_fill<T>), dim3(1024), dim3(256), 0, s, a.P, 3 * V, T(0));  // P_0 = 0
   if (hipMemcpyAsync(a.R, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
     p->err = "copy of the starting dual point failed";
     return BQ_EDEVICE;
   }
   const int max_launch = (has_u && nonneg) ? p->max_passes - 1 : 0;  // SSN passes per dual iteration
-  double t = 1.0;
-  for (int k = 0; k <= n_iter; ++k) {
-    const bool last = (k == n_iter);
-    if (last) {  // x(P_K): divergence of P_K itself
-      if (hipMemcpyAsync(a.R, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
-        p->err = "copy failed";
-        return BQ_EDEVICE;
-      }
-    }
+  // divergence + root finding for the current momentum R (all arguments are
+  // iteration invariant: the momentum coefficient lives on the device)
+  auto primal = [&]() {
     hipLaunchKernelGGL((k_div<T>), g, b, 0, s, a);
     hipLaunchKernelGGL(k_px_after_div, dim3(1), dim3(256), 0, s, p->st, (const double*)p->partial, p->np,
                        p->max_passes);
@@ -397,12 +408,33 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
       hipLaunchKernelGGL(k_px_after_ssn, dim3(1), dim3(256), 0, s, p->st, (const double*)p->partial, p->np,
                          p->max_passes);
     }
-    if (last) break;
-    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-    a.mom = (t - 1.0) / tn;
-    t = tn;
-    hipLaunchKernelGGL((k_dual<T>), g, b, 0, s, a);
+  };
+  if (n_iter > 0) {
+    // one dual iteration captured as a graph and replayed n_iter times
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      primal();
+      hipLaunchKernelGGL((k_dual<T>), g, b, 0, s, a);
+      ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
+    }
+    ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    for (int k = 0; ok && k < n_iter; ++k) ok = hipGraphLaunch(exec, s) == hipSuccess;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+      (void)hipGetLastError();
+      p->err = "graph capture or launch of the dual iteration failed";
+      return BQ_EDEVICE;
+    }
   }
+  // x(P_K): divergence of P_K itself, then the projection
+  if (hipMemcpyAsync(a.R, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    p->err = "copy failed";
+    return BQ_EDEVICE;
+  }
+  primal();
   hipLaunchKernelGGL((k_out<T>), g, b, 0, s, a);
   if (hipGetLastError() != hipSuccess) {
     p->err = "kernel launch failed";
@@ -431,6 +463,8 @@ void free_prox(bq_prox* p) {
   if (!p) return;
   void* ptrs[] = {p->a, p->P, p->R, p->partial, p->st};
   for (void* q : ptrs) if (q) (void)hipFree(q);
+  if (p->ev) (void)hipEventDestroy(p->ev);
+  if (p->own) (void)hipStreamDestroy(p->own);
   delete p;
 }
 
@@ -457,12 +491,18 @@ bq_status bq_prox_create(int nz, int ny, int nx, int precision, void* stream, bq
     g_prox_create_error = "out of device memory";
     return BQ_ENOMEM;
   }
+  if (hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev, hipEventDisableTiming) != hipSuccess) {
+    free_prox(p);
+    g_prox_create_error = "could not create the library stream";
+    return BQ_EDEVICE;
+  }
   *out = p;
   return BQ_OK;
 }
 
 bq_status bq_prox_destroy(bq_prox* p) {
-  if (p) (void)hipStreamSynchronize(p->stream);
+  if (p) (void)hipStreamSynchronize(p->own);
   free_prox(p);
   return BQ_OK;
 }

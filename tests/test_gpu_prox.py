@@ -117,3 +117,29 @@ def test_wprox_rejects_bad_arguments(dev):
     with pytest.raises(BQError):
         px(v, 1.0, None, 0.0)
     px.close()
+
+
+def test_wprox_graph_replays_are_stable(dev):
+    """The dual iteration runs as a captured graph replayed n_iter times;
+    repeated calls with unrelated eager GPU work and synchronisations in
+    between give bitwise identical results that match the oracle."""
+    from paper_2307_02043_amd import WProx
+    shape = (18, 20, 22)
+    v, u = _inputs(shape, 9)
+    ref = tp.wprox(v, 0.6, u, 1.5e-3, "iso", "nonneg", n_iter=25)
+    px = WProx(shape, "f64")
+    vt = torch.from_numpy(v).to(dev)
+    ut = torch.from_numpy(u).to(dev)
+    first = None
+    for rep in range(4):
+        junk = torch.randn(1 << 20, device=dev).cumsum(0)  # eager work between replays
+        torch.cuda.synchronize()
+        x, info = px(vt, 0.6, ut, 1.5e-3, "iso", "nonneg", 25)
+        torch.cuda.synchronize()
+        if first is None:
+            first = x.clone()
+            assert _rel(x.cpu().numpy(), ref) < 1e-10
+        else:
+            assert torch.equal(x, first), rep
+        del junk
+    px.close()
