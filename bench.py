@@ -37,19 +37,98 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes of one pass for one system and one application of G,
 # in units of V = N^3 complex elements (x the complex element size).  The
 # z passes depend on the prologue/epilogue; the figures are those of the
-# solver matvecs, which are the bulk of the launches.
+# solver matvecs, which are the bulk of the launches.  The transfer function
+# is counted as one octant per system application (its symmetry leaves one
+# independent octant of the padded grid); the batched launches read the full
+# eight parity classes once per launch, which at a batch of 16 is 0.5 V per
+# system.
 PASS_UNITS = {
     "zf": 3.5,   # read v (1) + x (real, 0.5); write 2 parity classes (2)
     "xf": 6.0,   # read 2, write 4
-    "yc": 16.0,  # read 4, write 4, transfer function 8 (once per system)
+    "yc": 9.0,   # read 4, write 4, transfer function 1
     "xi": 6.0,   # read 4, write 2
     "zi": 5.0,   # read 2 + v/s (1) + rhat or s (1); write 1
-    "xy": 12.0,  # fused plane pass: read 2, write 2, transfer function 8
+    "xy": 5.0,   # fused plane pass: read 2, write 2, transfer function 1
 }
+# Whole-call model: 28.5 V per application of G (the five passes above) and
+# about 13 V of fused vector updates per BiCGSTAB iteration.
+G_UNITS = 28.5
+ITER_VEC_UNITS = 13.0
+# Non-packed FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x
+# 2.4 GHz.  The code is built with packed FP32 disabled, so the 157.3
+# TFLOP/s packed figure is not reachable by it.
+FP32_VALU_PEAK_TFLOPS = 78.6
+
+
+def yc_flops_per_line(N):
+    """Radix-2 flop convention (5 M log2 M per complex M-point FFT) for one
+    padded y line of the convolution pass: forward FFT, transfer-function
+    product (6 flops per point), inverse FFT, with M = 2N."""
+    M = 2 * N
+    return 2 * 5 * M * np.log2(M) + 6 * M
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def copy_calibration(dev, mib):
+    """A plain copy of a known size: one read and one write of `mib` MiB, run
+    as an elementwise negation so that it is an ordinary kernel dispatch
+    (not a DMA copy) whose HBM counters can be read like the solver's."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 x neg of {n * 4} bytes")
+    del src, dst
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ls_grad_128cubed_b16_f32_hbm_traffic.txt")
+
+
+def source_digest():
+    """SHA-256 over the HIP sources and the C header, to tell whether the
+    kernels are still those the traffic counters were taken on."""
+    import hashlib
+    hs = hashlib.sha256()
+    cs = os.path.join(ROOT, "paper_2307_02043_amd", "csrc")
+    files = sorted(f for f in os.listdir(cs) if f.endswith((".hip", ".h")))
+    for f in files:
+        with open(os.path.join(cs, f), "rb") as fh:
+            hs.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "bq.h"), "rb") as fh:
+        hs.update(fh.read())
+    return hs.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio of the
+    known size of a plain copy to what the same counter read for it), or
+    None when the summary is missing or the sources have changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, _, v = line.strip().partition(" ")
+            kv[k] = v.strip()
+    if kv.get("csrc_sha256") != source_digest() or kv.get("kernel") != kernel:
+        return None
+    cb = float(kv["copy_bytes"])
+    ff = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
+    fw = cb / (float(kv["copy_write_kib"]) * 1024.0)
+    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024.0 * ff
+    write = float(kv["write_kib_per_dispatch"]) * 1024.0 * fw
+    return {"bytes_per_launch": round(fetch + write), "fetch_bytes": round(fetch),
+            "write_bytes": round(write), "fetch_scale": round(ff, 4), "write_scale": round(fw, 4),
+            "dispatches": int(kv.get("dispatches", 0))}
 
 
 def main():
@@ -64,6 +143,9 @@ def main():
                     help="BiCGSTAB iterations of the oracle sample (0: skip)")
     ap.add_argument("--prox-workload", default="c5_ls256_f32",
                     help="workload whose weighted prox is timed alongside ('' to skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy of this many MiB (reference for the "
+                         "HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -80,6 +162,8 @@ def main():
     w = syn.WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration > 0:
+        copy_calibration(dev, args.copy_calibration)
     N, B = w.N, w.B
     V = N ** 3
     log(f"workload {w.name}: N={N} B={B} of L={w.L}")
@@ -137,15 +221,35 @@ def main():
     csz = 8  # complex64
     alg_bytes = apps * PASS_UNITS[dom] * V * csz
     achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
-    reg = N in (16, 32, 64, 128, 256)  # register-resident z/y passes on power-of-two grids
-    kname = {"yc": "k_yc_r" if reg else "k_yc", "zf": "k_zf_r" if reg else "k_zf",
-             "zi": "k_zi_r" if reg else "k_zi", "xf": "k_xf", "xi": "k_xi", "xy": "k_xy"}[dom]
+    pad = N in (16, 32, 64, 128)  # padded-line register kernels for the z and y passes
+    reg = pad or N == 256         # parity-split register kernels
+    sfx = "_p" if pad else "_r" if reg else ""
+    kname = {"yc": "k_yc" + sfx, "zf": "k_zf" + sfx, "zi": "k_zi" + sfx,
+             "xf": "k_xf", "xi": "k_xi", "xy": "k_xy"}[dom]
+    avg_ms = pass_ms[dom] / pass_n[dom]
     roofline = {"bound": "hbm", "kernel": f"{kname}<float,{N}>", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None,
                 "bytes_per_system_application": PASS_UNITS[dom] * V * csz,
                 "system_applications": apps, "launches": pass_n[dom],
-                "avg_launch_ms": round(pass_ms[dom] / pass_n[dom], 4)}
+                "avg_launch_ms": round(avg_ms, 4)}
+    tr = measured_traffic(f"{kname}<float,{N}>")
+    if tr is not None:
+        roofline["traffic"] = tr["bytes_per_launch"]
+        tr["measured_gbs"] = round(tr["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_detail"] = tr
+    if dom == "yc":
+        # the same launches against the vector-ALU roof (4 classes x N^2 lines per system)
+        flops = apps * 4 * N * N * yc_flops_per_line(N)
+        tf = flops / (pass_ms[dom] * 1e-3) / 1e12
+        roofline["alu_view"] = {"achieved": round(tf, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4),
+                                "flops_per_line": yc_flops_per_line(N)}
+    whole_bytes = (apps * G_UNITS + iters * ITER_VEC_UNITS) * V * csz
+    whole = whole_bytes / elapsed / 1e9
+    whole_call = {"scope": "whole gradient call, model bytes", "achieved": round(whole, 1),
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(whole / HBM_PEAK_GBS, 4),
+                  "bytes_per_step": whole_bytes / args.steps}
     ctx.close()
 
     # ---- plain FP64 path ----------------------------------------------------
@@ -222,6 +326,7 @@ def main():
                                 f"fields, FP64 reductions, BiCGSTAB tol {w.tol:g}"),
                    "grid": N, "batch": B, "illuminations": w.L, "tol": w.tol},
         "roofline": roofline,
+        "whole_call": whole_call,
         "cpu_baseline": cpu,
         "plain_f64": plain,
         "speedup_vs_plain_f64": (round(value / plain["value"], 2) if plain else None),

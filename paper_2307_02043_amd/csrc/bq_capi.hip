@@ -1,6 +1,7 @@
 // C ABI of the bq library: contexts, argument checking, and the host-side
 // driver of the batched and per-illumination ("plain") solve paths.
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -57,6 +58,10 @@ struct bq_ctx {
   std::vector<SysState> hstate;
   std::vector<C<double>> hinc;
   PassTimer timer;
+  // iterations the previous batched forward / adjoint solve took: the next
+  // solve checks for convergence first after that many iterations, then
+  // after every iteration (0: no history, check every 4)
+  int hint[2] = {0, 0};
 };
 
 namespace {
@@ -198,13 +203,25 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
   a.mask = RUN_ALL;
   if (green_apply<T>(a, c->stream, &c->timer)) return check_launch(c, "green_apply(init)");
   sc_init(B, c->state, c->part_mv, c->np_mv, part_b, c->np_vec, bfix, c->g.tol, c->g.max_iter, c->stream);
+  // The scalar step that tests convergence and forms beta closes each pass
+  // (and is issued once here for the first), so that a host check right
+  // after a pass already sees its outcome.
+  sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
   if (bq_status s = check_launch(c, "init")) return s;
 
-  const int chunk = plain ? 1 : 4;
+  // Host checks of the convergence flags (a device-to-host copy and a stream
+  // synchronisation each): every iteration on the plain path; on the batched
+  // path first after the iteration count of the previous solve of the same
+  // kind, then every iteration, or every 4 iterations without history.
+  // Systems that have stopped skip their work inside the kernels, so a late
+  // check costs only near-empty launches.
+  int& hint = c->hint[fwd ? 0 : 1];
   const int max_loops = c->g.max_iter + 2;
-  for (int it = 0; it < max_loops; it += chunk) {
+  int done_iters = 0;
+  for (int it = 0; it < max_loops;) {
+    const int chunk = plain ? 1 : it == 0 && hint > 0 ? hint : hint > 0 ? 1 : 4;
+    it += chunk;
     for (int k = 0; k < chunk; ++k) {
-      sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
       c->timer.start(P_VEC, c->stream);
       vec_p<T>(va, c->stream);
       c->timer.stop(c->stream);
@@ -232,6 +249,7 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
       c->timer.start(P_VEC, c->stream);
       vec_xr<T>(va, c->stream);
       c->timer.stop(c->stream);
+      sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
     }
     if (bq_status s = check_launch(c, "bicgstab iteration")) return s;
     HIPCHK(c, hipMemcpyAsync(c->hstate.data(), c->state, B * sizeof(SysState), hipMemcpyDeviceToHost, c->stream));
@@ -241,6 +259,8 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
     for (int b = 0; b < B; ++b) running |= (c->hstate[b].status == SYS_RUNNING);
     if (!running) break;
   }
+  for (int b = 0; b < B; ++b) done_iters = std::max(done_iters, c->hstate[b].iters);
+  if (!plain) hint = std::max(1, done_iters);
   // a system still running after max_iter + 2 loops cannot happen (sc_beta
   // stops at max_iter); treat it as not converged defensively
   return BQ_OK;

@@ -52,29 +52,47 @@ __global__ void __launch_bounds__(NT) k_zf(PassArgs<T> a) {
   if (sys_skip(a.state, a.mask, b)) return;
   for (int i = tid; i < N; i += NT) { tw[i] = a.twN[i]; th[i] = a.twH[i]; }
   const size_t V = (size_t)N * N * N;
+  // Prologue: one loop per mode, so that all loads are in flight before use.
   C<T> orig[EPT];
+  auto valid = [&](int s) { return (TOT % NT) == 0 || tid + s * NT < TOT; };
+  auto zof = [&](int s) { return (tid + s * NT) / TX; };
+  auto xof = [&](int s) { return x0 + (tid + s * NT) - zof(s) * TX; };
+  auto nof = [&](int s) { return ((size_t)zof(s) * N + y) * N + xof(s); };
+  switch (a.zf_mode) {
+    case ZF_XV: {
+      T xr[EPT];
 #pragma unroll
-  for (int s = 0; s < EPT; ++s) {
-    const int e = tid + s * NT;
-    if ((TOT % NT) == 0 || e < TOT) {
-      const int z = e / TX, xo = e - z * TX, x = x0 + xo;
-      const size_t n = ((size_t)z * N + y) * N + x;
-      C<T> val;
-      switch (a.zf_mode) {
-        case ZF_XV: val = a.vin[b * V + n] * a.xpot[n]; break;
-        case ZF_XUIN: {
-          const C<double>* t = a.inc + (size_t)b * 3 * N;
-          C<double> u = cmul(cmul(t[x], t[N + y]), t[2 * N + z]);
-          val = cvt<T>(u) * a.xpot[n];
-        } break;
-        case ZF_DETCONJ:
-          val = (z == N - 1) ? conj(a.rdet[(size_t)b * N * N + (size_t)y * N + x]) : C<T>{0, 0};
-          break;
-        case ZF_V: val = a.vin[b * V + n]; break;
-        default: val = conj(a.vin[b * V + n]); break;
-      }
-      orig[s] = val;
-    }
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) { orig[s] = a.vin[b * V + nof(s)]; xr[s] = a.xpot[nof(s)]; }
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) orig[s] = orig[s] * xr[s];
+    } break;
+    case ZF_XUIN: {
+      const C<double>* t = a.inc + (size_t)b * 3 * N;
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          const C<double> u = cmul(cmul(t[xof(s)], t[N + y]), t[2 * N + zof(s)]);
+          orig[s] = cvt<T>(u) * a.xpot[nof(s)];
+        }
+    } break;
+    case ZF_DETCONJ:
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s))
+          orig[s] = (zof(s) == N - 1) ? conj(a.rdet[(size_t)b * N * N + (size_t)y * N + xof(s)]) : C<T>{0, 0};
+      break;
+    case ZF_V:
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) orig[s] = a.vin[b * V + nof(s)];
+      break;
+    default:
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) orig[s] = conj(a.vin[b * V + nof(s)]);
+      break;
   }
   for (int pz = 0; pz < 2; ++pz) {
 #pragma unroll
@@ -307,38 +325,64 @@ __global__ void __launch_bounds__(NT) k_zi(PassArgs<T> a) {
     }
     __syncthreads();
   }
+  // Epilogue: one loop per mode (operand loads first), FP64 products in
+  // ascending s.
   double red[3] = {0.0, 0.0, 0.0};
   const int mode = a.zi_mode;
+  auto valid = [&](int s) { return (TOT % NT) == 0 || tid + s * NT < TOT; };
+  auto nof = [&](int s) {
+    const int e = tid + s * NT, z = e / TX, xo = e - z * TX;
+    return (size_t)b * V + ((size_t)z * N + y) * N + x0 + xo;
+  };
+  switch (mode) {
+    case ZI_G:
 #pragma unroll
-  for (int s = 0; s < EPT; ++s) {
-    const int e = tid + s * NT;
-    if ((TOT % NT) == 0 || e < TOT) {
-      const int z = e / TX, xo = e - z * TX;
-      const size_t n = (size_t)b * V + ((size_t)z * N + y) * N + x0 + xo;
-      const C<T> gw = acc[s];
-      if (mode == ZI_G) {
-        a.out[n] = gw;
-      } else if (mode == ZI_GCONJ) {
-        a.out[n] = conj(gw);
-      } else if (mode == ZI_AV_RHAT) {
-        const C<T> o = a.vz[n] - gw;
-        a.out[n] = o;
-        const C<T> rh = a.rhat[n];
-        red[0] += (double)rh.x * o.x + (double)rh.y * o.y;
-        red[1] += (double)rh.x * o.y - (double)rh.y * o.x;
-      } else if (mode == ZI_AS_TS) {
-        const C<T> sv = a.vz[n];
-        const C<T> o = sv - gw;
-        a.out[n] = o;
-        red[0] += (double)o.x * sv.x + (double)o.y * sv.y;
-        red[1] += (double)o.x * sv.y - (double)o.y * sv.x;
-        red[2] += (double)o.x * o.x + (double)o.y * o.y;
-      } else {  // ZI_G_NORM
-        a.out[n] = gw;
-        if (a.out2) a.out2[n] = gw;
-        red[2] += (double)gw.x * gw.x + (double)gw.y * gw.y;
-      }
-    }
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) a.out[nof(s)] = acc[s];
+      break;
+    case ZI_GCONJ:
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) a.out[nof(s)] = conj(acc[s]);
+      break;
+    case ZI_AV_RHAT: {
+      C<T> o[EPT], rh[EPT];
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) { o[s] = a.vz[nof(s)]; rh[s] = a.rhat[nof(s)]; }
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          o[s] = o[s] - acc[s];
+          a.out[nof(s)] = o[s];
+          red[0] += (double)rh[s].x * o[s].x + (double)rh[s].y * o[s].y;
+          red[1] += (double)rh[s].x * o[s].y - (double)rh[s].y * o[s].x;
+        }
+    } break;
+    case ZI_AS_TS: {
+      C<T> sv[EPT];
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) sv[s] = a.vz[nof(s)];
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          const C<T> o = sv[s] - acc[s];
+          a.out[nof(s)] = o;
+          red[0] += (double)o.x * sv[s].x + (double)o.y * sv[s].y;
+          red[1] += (double)o.x * sv[s].y - (double)o.y * sv[s].x;
+          red[2] += (double)o.x * o.x + (double)o.y * o.y;
+        }
+    } break;
+    default:  // ZI_G_NORM
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          a.out[nof(s)] = acc[s];
+          if (a.out2) a.out2[nof(s)] = acc[s];
+          red[2] += (double)acc[s].x * acc[s].x + (double)acc[s].y * acc[s].y;
+        }
+      break;
   }
   if (mode >= ZI_AV_RHAT) {
     block_sum<NT, 3>(red, red_scratch);

@@ -29,6 +29,115 @@ constexpr int RT = 256;  // threads per workgroup
 template <typename T>
 __device__ inline C<T> cvt_r(C<double> a) { return C<T>{(T)a.x, (T)a.y}; }
 
+// Prologue of the z-forward passes: the H values z = j + R2 m (m < H) of
+// line L = y N + x of system b.  Each mode has a loop of its own so that all
+// loads of a thread are in flight before the first use.
+template <typename T, int N, int R2, int H>
+__device__ __forceinline__ void zf_prologue(const PassArgs<T>& a, int b, int j, int L, C<T>* d) {
+  const size_t N2 = (size_t)N * N, V = N2 * N;
+  switch (a.zf_mode) {
+    case ZF_XV: {
+      const C<T>* v = a.vin + (size_t)b * V + L;
+      const T* xp = a.xpot + L;
+      T xr[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        d[m] = v[(size_t)(j + R2 * m) * N2];
+        xr[m] = xp[(size_t)(j + R2 * m) * N2];
+      }
+#pragma unroll
+      for (int m = 0; m < H; ++m) d[m] = d[m] * xr[m];
+    } break;
+    case ZF_XUIN: {
+      const int y = L / N, x = L - y * N;
+      const C<double>* t = a.inc + (size_t)b * 3 * N;
+      const C<double> txy = cmul(t[x], t[N + y]);
+      const T* xp = a.xpot + L;
+      T xr[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) xr[m] = xp[(size_t)(j + R2 * m) * N2];
+#pragma unroll
+      for (int m = 0; m < H; ++m) d[m] = cvt_r<T>(cmul(txy, t[2 * N + j + R2 * m])) * xr[m];
+    } break;
+    case ZF_DETCONJ: {
+      const C<T> r = conj(a.rdet[(size_t)b * N2 + L]);
+#pragma unroll
+      for (int m = 0; m < H; ++m) d[m] = (j + R2 * m == N - 1) ? r : C<T>{0, 0};
+    } break;
+    case ZF_V: {
+      const C<T>* v = a.vin + (size_t)b * V + L;
+#pragma unroll
+      for (int m = 0; m < H; ++m) d[m] = v[(size_t)(j + R2 * m) * N2];
+    } break;
+    default: {
+      const C<T>* v = a.vin + (size_t)b * V + L;
+#pragma unroll
+      for (int m = 0; m < H; ++m) d[m] = conj(v[(size_t)(j + R2 * m) * N2]);
+    } break;
+  }
+}
+
+// Epilogue of the z-inverse passes: G w at z = j + R2 m (m < H) of line L of
+// system b, combined and stored by mode, with the FP64 products of the mode
+// accumulated into red (in ascending m).  Operand loads of a mode are all
+// issued before the first use.
+template <typename T, int N, int R2, int H>
+__device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, int L, const C<T>* gw,
+                                            double* red) {
+  const size_t N2 = (size_t)N * N, V = N2 * N;
+  C<T>* out = a.out + (size_t)b * V + L;
+  switch (a.zi_mode) {
+    case ZI_G:
+#pragma unroll
+      for (int m = 0; m < H; ++m) out[(size_t)(j + R2 * m) * N2] = gw[m];
+      break;
+    case ZI_GCONJ:
+#pragma unroll
+      for (int m = 0; m < H; ++m) out[(size_t)(j + R2 * m) * N2] = conj(gw[m]);
+      break;
+    case ZI_AV_RHAT: {
+      const C<T>* vz = a.vz + (size_t)b * V + L;
+      const C<T>* rhat = a.rhat + (size_t)b * V + L;
+      C<T> o[H], rh[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        o[m] = vz[(size_t)(j + R2 * m) * N2];
+        rh[m] = rhat[(size_t)(j + R2 * m) * N2];
+      }
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        o[m] = o[m] - gw[m];
+        out[(size_t)(j + R2 * m) * N2] = o[m];
+        red[0] += (double)rh[m].x * o[m].x + (double)rh[m].y * o[m].y;
+        red[1] += (double)rh[m].x * o[m].y - (double)rh[m].y * o[m].x;
+      }
+    } break;
+    case ZI_AS_TS: {
+      const C<T>* vz = a.vz + (size_t)b * V + L;
+      C<T> sv[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) sv[m] = vz[(size_t)(j + R2 * m) * N2];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const C<T> o = sv[m] - gw[m];
+        out[(size_t)(j + R2 * m) * N2] = o;
+        red[0] += (double)o.x * sv[m].x + (double)o.y * sv[m].y;
+        red[1] += (double)o.x * sv[m].y - (double)o.y * sv[m].x;
+        red[2] += (double)o.x * o.x + (double)o.y * o.y;
+      }
+    } break;
+    default: {  // ZI_G_NORM
+      C<T>* out2 = a.out2 ? a.out2 + (size_t)b * V + L : nullptr;
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        out[(size_t)(j + R2 * m) * N2] = gw[m];
+        if (out2) out2[(size_t)(j + R2 * m) * N2] = gw[m];
+        red[2] += (double)gw[m].x * gw[m].x + (double)gw[m].y * gw[m].y;
+      }
+    } break;
+  }
+}
+
 // z lines.  Line L = y N + x of the N^2 lines; element z at z N^2 + L.
 // grid (N^2 / LPW, 1, B)
 template <typename T, int N>
@@ -42,27 +151,8 @@ __global__ void __launch_bounds__(RT) k_zf_r(PassArgs<T> a) {
   for (int i = tid; i < N; i += RT) { tw[i] = a.twN[i]; th[i] = a.twH[i]; }
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
-  const int y = L / N, x = L - y * N;
   C<T> orig[R1], d[R1];
-#pragma unroll
-  for (int m = 0; m < R1; ++m) {
-    const int z = j + R2 * m;
-    const size_t n = (size_t)z * N2 + L;
-    C<T> val;
-    switch (a.zf_mode) {
-      case ZF_XV: val = a.vin[b * V + n] * a.xpot[n]; break;
-      case ZF_XUIN: {
-        const C<double>* t = a.inc + (size_t)b * 3 * N;
-        val = cvt_r<T>(cmul(cmul(t[x], t[N + y]), t[2 * N + z])) * a.xpot[n];
-      } break;
-      case ZF_DETCONJ:
-        val = (z == N - 1) ? conj(a.rdet[(size_t)b * N2 + L]) : C<T>{0, 0};
-        break;
-      case ZF_V: val = a.vin[b * V + n]; break;
-      default: val = conj(a.vin[b * V + n]); break;
-    }
-    orig[m] = val;
-  }
+  zf_prologue<T, N, R2, R1>(a, b, j, L, orig);
   __syncthreads();  // tables
   for (int pz = 0; pz < 2; ++pz) {
 #pragma unroll
@@ -152,33 +242,7 @@ __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
   }
   double red[3] = {0.0, 0.0, 0.0};
   const int mode = a.zi_mode;
-#pragma unroll
-  for (int m = 0; m < R1; ++m) {
-    const size_t n = (size_t)b * V + (size_t)(j + R2 * m) * N2 + L;
-    const C<T> gw = acc[m];
-    if (mode == ZI_G) {
-      a.out[n] = gw;
-    } else if (mode == ZI_GCONJ) {
-      a.out[n] = conj(gw);
-    } else if (mode == ZI_AV_RHAT) {
-      const C<T> o = a.vz[n] - gw;
-      a.out[n] = o;
-      const C<T> rh = a.rhat[n];
-      red[0] += (double)rh.x * o.x + (double)rh.y * o.y;
-      red[1] += (double)rh.x * o.y - (double)rh.y * o.x;
-    } else if (mode == ZI_AS_TS) {
-      const C<T> sv = a.vz[n];
-      const C<T> o = sv - gw;
-      a.out[n] = o;
-      red[0] += (double)o.x * sv.x + (double)o.y * sv.y;
-      red[1] += (double)o.x * sv.y - (double)o.y * sv.x;
-      red[2] += (double)o.x * o.x + (double)o.y * o.y;
-    } else {  // ZI_G_NORM
-      a.out[n] = gw;
-      if (a.out2) a.out2[n] = gw;
-      red[2] += (double)gw.x * gw.x + (double)gw.y * gw.y;
-    }
-  }
+  zi_epilogue<T, N, R2, R1>(a, b, j, L, acc, red);
   if (mode >= ZI_AV_RHAT) {
     block_sum<RT, 3>(red, red_scratch);
     if (tid == 0) {
@@ -196,6 +260,141 @@ __global__ void __launch_bounds__(RT) k_yc_r(PassArgs<T> a) { yc_body<T, N>(a); 
 template <typename T, int N>
 __global__ void __launch_bounds__(RT) k_zi_r(PassArgs<T> a) { zi_body<T, N>(a); }
 
+
+// ===========================================================================
+// Padded-line variants (N = 16..128): a strided line of N points is
+// transformed as one 2N-point line with zero upper half instead of two
+// pre-twiddled N-point lines.  Padded frequency k' = 2k + p lands in parity
+// class p at index k, and the sum over both classes of the conjugate-
+// twiddled N-point inverses equals the first N outputs of the 2N-point
+// inverse, so no input copy, accumulator or parity twiddle is needed.  The
+// zero half of the input and the unused half of the inverse's outputs are
+// removed by the compiler.
+// ===========================================================================
+template <int N> struct PadCfg { static constexpr bool ok = false; static constexpr int R1 = 1, R2 = 1; };
+#define BQ_PC(NN, A, B_) \
+  template <> struct PadCfg<NN> { static constexpr bool ok = true; static constexpr int R1 = A, R2 = B_; };
+BQ_PC(16, 8, 4)
+BQ_PC(32, 8, 8)
+BQ_PC(64, 16, 8)
+BQ_PC(128, 16, 16)
+#undef BQ_PC
+
+// W_{2N}^k for k < 2N from the half-angle table exp(-i pi n / N), n < N
+template <typename T, int N>
+__device__ inline void load_tw2(C<T>* tw2, const C<T>* twH, int tid) {
+  for (int i = tid; i < 2 * N; i += RT) {
+    const C<T> w = twH[i < N ? i : i - N];
+    tw2[i] = i < N ? w : C<T>{-w.x, -w.y};
+  }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(RT) k_zf_p(PassArgs<T> a) {
+  constexpr int M = 2 * N, R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, LS = M + 1, NI = R1 / R2;
+  constexpr int H = R1 / 2;  // nonzero inputs per thread
+  __shared__ C<T> lds[LPW * LS];
+  __shared__ C<T> tw2[M];
+  const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
+  if (sys_skip(a.state, a.mask, b)) return;
+  load_tw2<T, N>(tw2, a.twH, tid);
+  const size_t N2 = (size_t)N * N, V = N2 * N;
+  const int L = blockIdx.x * LPW + line;
+  C<T> d[R1];
+  zf_prologue<T, N, R2, H>(a, b, j, L, d);
+#pragma unroll
+  for (int m = H; m < R1; ++m) d[m] = C<T>{0, 0};
+  __syncthreads();  // twiddle table
+  line_fft<T, M, R1, R2, false>(d, &lds[line * LS], 1, j, tw2);
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      const int kp = (j + R2 * i) + R1 * k2;  // padded frequency
+      a.zh[(size_t)(b * 2 + (kp & 1)) * V + (size_t)(kp >> 1) * N2 + L] = d[i * R2 + k2];
+    }
+}
+
+// y columns of class (pz, px), line L = kz N + kx
+template <typename T, int N>
+__global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
+  constexpr int M = 2 * N, R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, LS = M + 1, NI = R1 / R2;
+  constexpr int H = R1 / 2;
+  __shared__ C<T> lds[LPW * LS];
+  __shared__ C<T> tw2[M];
+  // XCD-aware order: workgroup h runs on XCD h mod 8; the B systems of one
+  // (class, line block) take consecutive slots of the same XCD, so the
+  // transfer-function slab they share is fetched into that XCD's L2 once.
+  constexpr int NLB = N * N / LPW;
+  const int h = blockIdx.x, sl = h >> 3;
+  const int b = sl % a.B;
+  const int q = (sl / a.B) * 8 + (h & 7);
+  const int cls = q / NLB, lb = q - cls * NLB, pz = cls >> 1, px = cls & 1;
+  const int tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
+  if (sys_skip(a.state, a.mask, b)) return;
+  load_tw2<T, N>(tw2, a.twH, tid);
+  const size_t N2 = (size_t)N * N, V = N2 * N;
+  const int L = lb * LPW + line;
+  const int kz = L / N, kx = L - kz * N;
+  C<T>* col = a.xh + ((size_t)b * 4 + cls) * V + (size_t)kz * N2 + kx;
+  C<T> d[R1];
+#pragma unroll
+  for (int m = 0; m < R1; ++m) d[m] = (m < H) ? col[(size_t)(j + R2 * m) * N] : C<T>{0, 0};
+  __syncthreads();
+  line_fft<T, M, R1, R2, false>(d, &lds[line * LS], 1, j, tw2);
+  const C<T>* g0 = a.ghat + (size_t)((pz * 2 + 0) * 2 + px) * V + (size_t)kz * N2 + kx;
+  const C<T>* g1 = a.ghat + (size_t)((pz * 2 + 1) * 2 + px) * V + (size_t)kz * N2 + kx;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      const int kp = (j + R2 * i) + R1 * k2;
+      const C<T>* g = (kp & 1) ? g1 : g0;
+      d[i * R2 + k2] = cmul(d[i * R2 + k2], g[(size_t)(kp >> 1) * N]);
+    }
+  line_ifft<T, M, R1, R2>(d, &lds[line * LS], 1, j, tw2);
+#pragma unroll
+  for (int m = 0; m < H; ++m) col[(size_t)(j + R2 * m) * N] = d[m];
+}
+
+// z lines, inverse (first N outputs of the padded inverse), epilogue
+template <typename T, int N>
+__global__ void __launch_bounds__(RT) k_zi_p(PassArgs<T> a) {
+  constexpr int M = 2 * N, R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, LS = M + 1, NI = R1 / R2;
+  constexpr int H = R1 / 2;
+  __shared__ C<T> lds[LPW * LS];
+  __shared__ C<T> tw2[M];
+  __shared__ double red_scratch[(RT / 64) * 3];
+  const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
+  if (sys_skip(a.state, a.mask, b)) return;
+  load_tw2<T, N>(tw2, a.twH, tid);
+  const size_t N2 = (size_t)N * N, V = N2 * N;
+  const int L = blockIdx.x * LPW + line;
+  C<T> d[R1];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      const int kp = (j + R2 * i) + R1 * k2;
+      d[i * R2 + k2] = a.zh[(size_t)(b * 2 + (kp & 1)) * V + (size_t)(kp >> 1) * N2 + L];
+    }
+  __syncthreads();
+  line_ifft<T, M, R1, R2>(d, &lds[line * LS], 1, j, tw2);
+  double red[3] = {0.0, 0.0, 0.0};
+  const int mode = a.zi_mode;
+  zi_epilogue<T, N, R2, H>(a, b, j, L, d, red);
+  if (mode >= ZI_AV_RHAT) {
+    block_sum<RT, 3>(red, red_scratch);
+    if (tid == 0) {
+      double* p = a.partial + ((size_t)b * gridDim.x + blockIdx.x) * 4;
+      p[0] = red[0];
+      p[1] = red[1];
+      p[2] = red[2];
+      p[3] = 0.0;
+    }
+  }
+}
+
 template <typename T>
 bool reg_supported(int N) {
   switch (N) {
@@ -205,11 +404,11 @@ bool reg_supported(int N) {
 }
 
 int reg_num_partials(int N) {
-  switch (N) {
-    case 16: return N * N / (RT / RegCfg<16>::R2);
-    case 32: return N * N / (RT / RegCfg<32>::R2);
-    case 64: return N * N / (RT / RegCfg<64>::R2);
-    case 128: return N * N / (RT / RegCfg<128>::R2);
+  switch (N) {  // grid of the z-inverse kernel (padded variant up to 128)
+    case 16: return N * N / (RT / PadCfg<16>::R2);
+    case 32: return N * N / (RT / PadCfg<32>::R2);
+    case 64: return N * N / (RT / PadCfg<64>::R2);
+    case 128: return N * N / (RT / PadCfg<128>::R2);
     case 256: return N * N / (RT / RegCfg<256>::R2);
     default: return -1;
   }
@@ -217,10 +416,14 @@ int reg_num_partials(int N) {
 
 template <typename T, int N>
 static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bool fused_xy) {
-  constexpr int LPW = RT / RegCfg<N>::R2;
+  constexpr bool PAD = PadCfg<N>::ok;
+  constexpr int LPW = RT / (PAD ? PadCfg<N>::R2 : RegCfg<N>::R2);
   const dim3 blk(RT);
   if (tm) tm->start(P_ZF, st);
-  hipLaunchKernelGGL((k_zf_r<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+  if constexpr (PAD)
+    hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_zf_r<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
   if (fused_xy) {
     if (tm) { tm->stop(st); tm->start(P_XY, st); }
     xy_fused_launch<T>(a, st);
@@ -230,12 +433,18 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
     if (tm) { tm->stop(st); tm->start(P_XF, st); }
     launch_xf_stockham<T, N>(a, st);
     if (tm) { tm->stop(st); tm->start(P_YC, st); }
-    hipLaunchKernelGGL((k_yc_r<T, N>), dim3(N * N / LPW, 1, 4 * a.B), blk, 0, st, a);
+    if constexpr (PAD)  // 4 N^2 / LPW is a multiple of 8 for every padded size
+      hipLaunchKernelGGL((k_yc_p<T, N>), dim3(4 * (N * N / LPW) * a.B), blk, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_yc_r<T, N>), dim3(N * N / LPW, 1, 4 * a.B), blk, 0, st, a);
     if (tm) { tm->stop(st); tm->start(P_XI, st); }
     launch_xi_stockham<T, N>(a, st);
   }
   if (tm) { tm->stop(st); tm->start(P_ZI, st); }
-  hipLaunchKernelGGL((k_zi_r<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+  if constexpr (PAD)
+    hipLaunchKernelGGL((k_zi_p<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_zi_r<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
   if (tm) tm->stop(st);
 }
 
