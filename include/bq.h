@@ -157,10 +157,16 @@ bq_status bq_loss(bq_ctx* ctx, const void* x, const void* y, const int* idx, int
 bq_status bq_green_apply(bq_ctx* ctx, const void* v, void* out, int B, int adjoint);
 
 /* Device timing of the passes of the Green's operator (HIP events recorded
- * on the context stream around every launch).  enable != 0 clears the
- * counters and starts timing; 0 stops it.  bq_timing_get returns the summed
- * duration (ms) and the number of launches of one pass since the last
- * enable.  Errors: BQ_EINVAL. */
+ * on the context stream around every launch of a timed pass).  enable is a
+ * bit mask over bq_pass (bit p times pass p; BQ_TIMING_ALL times all); a
+ * nonzero mask clears the counters and starts timing, 0 stops it.  Each
+ * timed launch adds two event records to the stream, so time only the
+ * passes of interest where the event overhead matters.  Events are read
+ * back lazily: bq_timing (either value) synchronises the context stream and
+ * brings the totals up to date.  bq_timing_get then returns the summed duration (ms)
+ * and the number of launches of one pass since the last enable.
+ * Errors: BQ_EINVAL (no context, mask outside [0, BQ_TIMING_ALL], pass out
+ * of range). */
 typedef enum {
   BQ_PASS_ZF = 0,  /* z lines, forward, with the input prologue          */
   BQ_PASS_XF = 1,  /* x rows, forward (split path)                        */
@@ -171,6 +177,7 @@ typedef enum {
   BQ_PASS_VEC = 6, /* BiCGSTAB vector updates                             */
   BQ_PASS_COUNT = 7
 } bq_pass;
+#define BQ_TIMING_ALL ((1 << BQ_PASS_COUNT) - 1)
 bq_status bq_timing(bq_ctx* ctx, int enable);
 bq_status bq_timing_get(const bq_ctx* ctx, int pass, double* total_ms, long long* launches);
 

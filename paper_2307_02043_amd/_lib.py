@@ -20,6 +20,7 @@ BQ_FLAG_FUSED_XY = 2
 BQ_TV_ISO, BQ_TV_ANISO = 0, 1
 BQ_SET_NONE, BQ_SET_NONNEG = 0, 1
 PASS_NAMES = ("zf", "xf", "yc", "xi", "zi", "xy", "vec")
+BQ_TIMING_ALL = (1 << len(PASS_NAMES)) - 1
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
             "bq_grad", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",

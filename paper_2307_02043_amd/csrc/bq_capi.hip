@@ -55,8 +55,10 @@ struct bq_ctx {
   double* part_mv = nullptr;
   double* part_vec = nullptr;
   double* part_det = nullptr;
-  std::vector<SysState> hstate;
-  std::vector<C<double>> hinc;
+  // pinned host staging (hipHostMalloc), sized with the batch capacity
+  SysState* hstate = nullptr;
+  C<double>* hinc = nullptr;
+  double* hpart = nullptr;
   PassTimer timer;
   // iterations the previous batched forward / adjoint solve took: the next
   // solve checks for convergence first after that many iterations, then
@@ -89,6 +91,8 @@ void free_batch(bq_ctx* c) {
   void** others[] = {&c->zh, &c->xh, &c->rdet, (void**)&c->inc, (void**)&c->state,
                      (void**)&c->part_mv, (void**)&c->part_vec, (void**)&c->part_det};
   for (void** p : others) { if (*p) (void)hipFree(*p); *p = nullptr; }
+  void** pinned[] = {(void**)&c->hstate, (void**)&c->hinc, (void**)&c->hpart};
+  for (void** p : pinned) { if (*p) (void)hipHostFree(*p); *p = nullptr; }
   c->Bcap = 0;
 }
 
@@ -108,15 +112,19 @@ bq_status ensure_capacity(bq_ctx* c, int B) {
     free_batch(c);
     return set_err(c, BQ_ENOMEM, "out of device memory (workspace)");
   }
+  if (hipHostMalloc((void**)&c->hstate, (size_t)B * sizeof(SysState)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hinc, (size_t)B * 3 * c->g.N * sizeof(C<double>)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hpart, (size_t)B * c->np_det * sizeof(double)) != hipSuccess) {
+    free_batch(c);
+    return set_err(c, BQ_ENOMEM, "out of pinned host memory");
+  }
   c->Bcap = B;
-  c->hstate.resize(B);
   return BQ_OK;
 }
 
 // Plane-wave factors exp(i kb d_a c_i), c_i = (i - (N-1)/2) h, per system.
 bq_status upload_incident(bq_ctx* c, const int* idx, int B) {
   const int N = c->g.N;
-  c->hinc.resize((size_t)B * 3 * N);
   for (int b = 0; b < B; ++b) {
     const bq_illum& d = c->dirs[idx[b]];
     const double comp[3] = {d.dx, d.dy, d.dz};
@@ -127,7 +135,7 @@ bq_status upload_incident(bq_ctx* c, const int* idx, int B) {
         c->hinc[((size_t)b * 3 + a) * N + i] = C<double>{(double)cosl(ph), (double)sinl(ph)};
       }
   }
-  HIPCHK(c, hipMemcpyAsync(c->inc, c->hinc.data(), c->hinc.size() * sizeof(C<double>),
+  HIPCHK(c, hipMemcpyAsync(c->inc, c->hinc, (size_t)B * 3 * N * sizeof(C<double>),
                            hipMemcpyHostToDevice, c->stream));
   return BQ_OK;
 }
@@ -252,9 +260,9 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
       sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
     }
     if (bq_status s = check_launch(c, "bicgstab iteration")) return s;
-    HIPCHK(c, hipMemcpyAsync(c->hstate.data(), c->state, B * sizeof(SysState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hstate, c->state, B * sizeof(SysState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->timer.collect();
+    c->timer.maybe_collect();
     bool running = false;
     for (int b = 0; b < B; ++b) running |= (c->hstate[b].status == SYS_RUNNING);
     if (!running) break;
@@ -354,7 +362,7 @@ bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out,
     }
     if (bq_status s = check_launch(c, "forward")) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->timer.collect();
+    c->timer.maybe_collect();
     record(c, stats, b0, nb, true, extra);
     for (int b = 0; b < nb; ++b) { stats[b0 + b].status_adj = 0; }
   }
@@ -375,7 +383,6 @@ bq_status do_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   const size_t N2 = (size_t)N * N;
   const bool born = c->g.model == BQ_MODEL_BORN;
   double total = 0.0;
-  std::vector<double> hpart;
   const int step = plain ? 1 : B;
   for (int b0 = 0; b0 < B; b0 += step) {
     const int nb = step;
@@ -401,12 +408,12 @@ bq_status do_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B
     detector<T>(nb, N, field, sub, c->inc, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det,
                 c->np_det, c->stream);
     if (bq_status s = check_launch(c, "loss")) return s;
-    hpart.resize((size_t)nb * c->np_det);
-    HIPCHK(c, hipMemcpyAsync(hpart.data(), c->part_det, hpart.size() * sizeof(double), hipMemcpyDeviceToHost,
+    const size_t npart = (size_t)nb * c->np_det;
+    HIPCHK(c, hipMemcpyAsync(c->hpart, c->part_det, npart * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->timer.collect();
-    for (double v : hpart) total += v;
+    c->timer.maybe_collect();
+    for (size_t i = 0; i < npart; ++i) total += c->hpart[i];
   }
   *loss = scale * total;
   if (st) std::memcpy(st, stats.data(), B * sizeof(bq_solve_stats));
@@ -425,7 +432,6 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   const size_t N2 = (size_t)N * N;
   const bool born = c->g.model == BQ_MODEL_BORN;
   double total_loss = 0.0;
-  std::vector<double> hpart;
   const int step = plain ? 1 : B;
   for (int b0 = 0; b0 < B; b0 += step) {
     const int nb = step;
@@ -469,12 +475,12 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
     gradient<T>(nb, N, born ? nullptr : (const C<T>*)c->f[F_U], c->inc, (const C<T>*)c->f[F_W], scale,
                 b0 > 0 ? 1 : 0, (T*)g, c->stream);
     if (bq_status s = check_launch(c, "grad")) return s;
-    hpart.resize((size_t)nb * c->np_det);
-    HIPCHK(c, hipMemcpyAsync(hpart.data(), c->part_det, hpart.size() * sizeof(double), hipMemcpyDeviceToHost,
+    const size_t npart = (size_t)nb * c->np_det;
+    HIPCHK(c, hipMemcpyAsync(c->hpart, c->part_det, npart * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->timer.collect();
-    for (double v : hpart) total_loss += v;
+    c->timer.maybe_collect();
+    for (size_t i = 0; i < npart; ++i) total_loss += c->hpart[i];
   }
   if (loss) *loss = scale * total_loss;
   if (st) std::memcpy(st, stats.data(), B * sizeof(bq_solve_stats));
@@ -495,7 +501,7 @@ bq_status do_green(bq_ctx* c, const void* v, void* out, int B, int adjoint) {
   if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
   if (bq_status s = check_launch(c, "green_apply")) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->timer.collect();
+  c->timer.maybe_collect();
   return BQ_OK;
 }
 
@@ -611,10 +617,12 @@ bq_status bq_green_apply(bq_ctx* c, const void* v, void* out, int B, int adjoint
 
 bq_status bq_timing(bq_ctx* c, int enable) {
   if (!c) return BQ_EINVAL;
+  if (enable < 0 || enable > BQ_TIMING_ALL) return set_err(c, BQ_EINVAL, "timing mask out of range");
   (void)hipStreamSynchronize(c->stream);
   c->timer.collect();
   if (enable) c->timer.reset();
   c->timer.on = enable != 0;
+  c->timer.mask = (unsigned)enable;
   return BQ_OK;
 }
 

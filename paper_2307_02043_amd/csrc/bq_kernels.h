@@ -18,6 +18,7 @@ enum PassId { P_ZF = 0, P_XF, P_YC, P_XI, P_ZI, P_XY, P_VEC, P_COUNT };
 
 struct PassTimer {
   bool on = false;
+  unsigned mask = 0;  // passes timed (bit p for pass p)
   std::vector<hipEvent_t> ev;
   std::vector<std::pair<int, size_t>> rec;  // (pass, index of the start event)
   size_t next = 0;
@@ -26,7 +27,7 @@ struct PassTimer {
   int open_pass = -1;
 
   void start(int pass, hipStream_t s) {
-    if (!on) return;
+    if (!on || !((mask >> pass) & 1u)) return;
     while (ev.size() < next + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
@@ -53,6 +54,11 @@ struct PassTimer {
     }
     rec.clear();
     next = 0;
+  }
+  // at the host synchronisation points of a call: read the events back only
+  // once many are pending, so that timing adds no per-call host work
+  void maybe_collect() {
+    if (rec.size() >= 4096) collect();
   }
   void reset() {
     for (int i = 0; i < P_COUNT; ++i) { total_ms[i] = 0.0; count[i] = 0; }

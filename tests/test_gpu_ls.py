@@ -208,3 +208,27 @@ def test_status_and_errors(dev):
     g0, _, info0 = ctx.grad(z, torch.from_numpy(y).to(dev), idx, 0.25)
     assert info0.status == 0 and all(i == 0 for i in info0.iters_fwd + info0.iters_adj)
     ctx.close()
+
+
+def test_pass_timing_mask(dev):
+    """bq_timing times exactly the passes of its mask; out-of-range masks fail."""
+    from paper_2307_02043_amd import _lib as L
+    lib = L.load()
+    N = 32
+    ctx = _ctx(N, np.array([[0.0, 0.0, 1.0]]), "f32")
+    v = torch.randn(2, N, N, N, dtype=torch.complex64, device=dev)
+    yc = L.PASS_NAMES.index("yc")
+    assert lib.bq_timing(ctx._h, 1 << yc) == 0
+    ctx.green(v)
+    ctx.green(v)
+    assert lib.bq_timing(ctx._h, 0) == 0
+    for pid, name in enumerate(L.PASS_NAMES):
+        ms, n = L.ct.c_double(), L.ct.c_longlong()
+        assert lib.bq_timing_get(ctx._h, pid, L.ct.byref(ms), L.ct.byref(n)) == 0
+        if name == "yc":
+            assert n.value == 2 and ms.value > 0
+        else:
+            assert n.value == 0
+    assert lib.bq_timing(ctx._h, L.BQ_TIMING_ALL + 1) == L.BQ_EINVAL
+    assert lib.bq_timing(ctx._h, -1) == L.BQ_EINVAL
+    ctx.close()
