@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY -- see the package docstring.
 
 Computes x = argmin_{x in C} 1/2 ||x - v||^2_B + lam TV(x) with
-B = tau I + U U^T (rank r in {0, 1}), C = R^N_+ or R^N, TV isotropic or
+B = tau I + U U^T (U with r >= 0 columns), C = R^N_+ or R^N, TV isotropic or
 anisotropic, following arXiv:2307.02043:
 
 * discrete TV and its dual form (Section 3.2 eqs. TViso/TVl1, Section 3.3
@@ -17,13 +17,17 @@ anisotropic, following arXiv:2307.02043:
   dual objective -2 lam d^T(x(P)), Lipschitz constant 8 D lam^2 / omega_min
   (Lemma 4.1), minimised by the accelerated projected gradient (FISTA)
   iteration with step 1 / Lipschitz, output x(P_K);
-* B^-1 applied with the Woodbury identity (Section 4.3);
-* prox^B_{iota_C}(w) = max(w - U beta* / tau, 0) with beta* the root of
-  phi(beta) = U^T (w - max(w - U beta / tau, 0)) + beta (Theorem 3.1 with
+* B^-1 applied with the Woodbury identity (Section 4.3):
+  B^-1 = I / tau - U (I_r + U^T U / tau)^-1 U^T / tau^2;
+* prox^B_{iota_C}(w) = max(w - U beta* / tau, 0) with beta* in R^r the root
+  of phi(beta) = U^T (w - max(w - U beta / tau, 0)) + beta (Theorem 3.1 with
   Sigma = tau I).  For r = 1 phi is continuous, piecewise linear and
   increasing with slope >= 1; the oracle finds its root exactly from the
-  sorted breakpoints (the library uses the semi-smooth Newton iteration of
-  Algorithm 4.3).
+  sorted breakpoints.  For r >= 2 phi is the gradient of a strongly convex
+  piecewise-quadratic function and the oracle takes Newton steps on its
+  pieces with backtracking until a full step stays on its piece, where the
+  step is the exact root (the library uses the semi-smooth Newton iteration
+  of Algorithm 4.3 in both cases).
 * omega_min = tau for B = tau I + U U^T when rank U < N.
 """
 from __future__ import annotations
@@ -96,23 +100,47 @@ def project_dual(P: np.ndarray, kind: str) -> np.ndarray:
 # metric tau I + u u^T
 # --------------------------------------------------------------------------
 
-def apply_B(y, tau, u):
+def _cols(u, shape):
+    """The metric's low-rank factor as an (r, V) array (r = 0 for None).
+
+    u is None, an image of the given shape (rank one) or an array of shape
+    (r,) + shape (columns u_1 .. u_r).
+    """
     if u is None:
-        return tau * y
-    return tau * y + u * np.sum(u * y)
+        return np.zeros((0, int(np.prod(shape))))
+    u = np.asarray(u, dtype=np.float64)
+    if u.shape == tuple(shape):
+        return u.reshape(1, -1)
+    return u.reshape(u.shape[0], -1)
+
+
+def apply_B(y, tau, u):
+    """(tau I + U U^T) y."""
+    U = _cols(u, y.shape)
+    return tau * y + (U.T @ (U @ y.ravel())).reshape(y.shape)
 
 
 def apply_B_inv(y, tau, u):
-    """Woodbury: B^-1 = I/tau - u (1 + u^T u / tau)^-1 u^T / tau^2."""
-    if u is None:
+    """Woodbury: B^-1 = I/tau - U (I_r + U^T U / tau)^-1 U^T / tau^2."""
+    U = _cols(u, y.shape)
+    if U.shape[0] == 0:
         return y / tau
-    m = 1.0 + np.sum(u * u) / tau
-    return y / tau - u * (np.sum(u * y) / m) / (tau * tau)
+    M = np.eye(U.shape[0]) + (U @ U.T) / tau
+    c = np.linalg.solve(M, U @ y.ravel())
+    return y / tau - (U.T @ c).reshape(y.shape) / (tau * tau)
 
 
 def phi(beta, w, tau, u):
-    """phi(beta) = u^T (w - max(w - u beta / tau, 0)) + beta (Theorem 3.1)."""
-    return float(np.sum(u * (w - np.maximum(w - u * beta / tau, 0.0))) + beta)
+    """phi(beta) = U^T (w - max(w - U beta / tau, 0)) + beta (Theorem 3.1).
+
+    Scalar for a rank-one u given as an image, a vector of length r otherwise."""
+    U = _cols(u, np.shape(w))
+    wf = np.ravel(w)
+    b = np.atleast_1d(np.asarray(beta, dtype=np.float64))
+    out = U @ (wf - np.maximum(wf - U.T @ b / tau, 0.0)) + b
+    if np.shape(u) == np.shape(w):
+        return float(out[0])
+    return out
 
 
 def root_phi_exact(w, tau, u):
@@ -154,12 +182,64 @@ def root_phi_exact(w, tau, u):
     return float(-inter[k - 1] / slope[k - 1])
 
 
+def _psi_fn(beta, wf, tau, U):
+    """Psi(beta) = 1/2 ||beta||^2 + beta^T U^T w + tau/2 ||max(w - U beta / tau, 0)||^2,
+    whose gradient is phi (Theorem 3.1)."""
+    z = np.maximum(wf - U.T @ beta / tau, 0.0)
+    return 0.5 * float(beta @ beta) + float(beta @ (U @ wf)) + 0.5 * tau * float(z @ z)
+
+
+def root_phi_rank(w, tau, u, max_iter=200):
+    """Root of phi for a metric factor of any rank r >= 1 (Theorem 3.1).
+
+    phi is the gradient of the strongly convex piecewise-quadratic Psi; on
+    the piece with active set A = {w - U beta / tau > 0} it is affine with
+    Jacobian H = I + U_A^T U_A / tau.  Newton steps -H^-1 phi with
+    backtracking on Psi (Armijo, factor 1/2) converge; when a full step keeps
+    the active set it lands on the root of that piece, i.e. the exact root.
+    """
+    wf = np.ravel(w)
+    U = _cols(u, np.shape(w))
+    r = U.shape[0]
+    beta = np.zeros(r)
+    for _ in range(max_iter):
+        z = wf - U.T @ beta / tau
+        A = z > 0
+        g = U @ (wf - np.maximum(z, 0.0)) + beta
+        H = np.eye(r) + (U[:, A] @ U[:, A].T) / tau
+        d = -np.linalg.solve(H, g)
+        psi0 = _psi_fn(beta, wf, tau, U)
+        slope = float(g @ d)
+        if slope >= 0.0:          # g = 0 to rounding: beta is the root
+            return beta
+        t = 1.0
+        while _psi_fn(beta + t * d, wf, tau, U) > psi0 + 1e-4 * t * slope and t > 1e-30:
+            t *= 0.5
+        beta_new = beta + t * d
+        if t == 1.0 and np.array_equal(wf - U.T @ beta_new / tau > 0, A):
+            return beta_new
+        beta = beta_new
+    raise RuntimeError("root_phi_rank did not terminate")
+
+
 def weighted_projection_nonneg(w, tau, u):
-    """prox^B_{iota_{R+}}(w) for B = tau I + u u^T (Theorem 3.1)."""
-    if u is None:
+    """prox^B_{iota_{R+}}(w) for B = tau I + U U^T (Theorem 3.1).
+
+    Returns (x, beta*): beta* scalar for a rank-one u given as an image, a
+    vector of length r otherwise (r = 0: plain projection, beta* = 0)."""
+    U = _cols(u, np.shape(w))
+    if U.shape[0] == 0:
         return np.maximum(w, 0.0), 0.0
-    beta = root_phi_exact(w, tau, u)
-    return np.maximum(w - u * beta / tau, 0.0), beta
+    if np.shape(u) == np.shape(w):
+        beta = root_phi_exact(w, tau, u)
+        return np.maximum(w - u * beta / tau, 0.0), beta
+    if U.shape[0] == 1:
+        b = root_phi_exact(w, tau, U[0].reshape(np.shape(w)))
+        beta = np.array([b])
+    else:
+        beta = root_phi_rank(w, tau, u)
+    x = np.maximum(np.ravel(w) - U.T @ beta / tau, 0.0).reshape(np.shape(w))
+    return x, beta
 
 
 # --------------------------------------------------------------------------
@@ -177,7 +257,9 @@ def _primal(P, v, tau, u, lam, cset):
 
 def wprox(v, tau, u, lam, kind="iso", cset="nonneg", n_iter=50, P0=None,
           return_dual=False):
-    """argmin_{x in C} 1/2 ||x - v||^2_{tau I + u u^T} + lam TV(x).
+    """argmin_{x in C} 1/2 ||x - v||^2_{tau I + U U^T} + lam TV(x).
+
+    u: None, a rank-one image, or the r columns of U as an (r,) + shape array.
 
     Accelerated projected gradient on the dual (Section 4.1), P_0 = R_1 = P0
     (zero by default), t_1 = 1, n_iter iterations, output x(P_K).

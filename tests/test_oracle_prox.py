@@ -9,8 +9,13 @@
 * weighted projection onto the nonnegative orthant under tau I + u u^T vs
   enumeration of all active sets with KKT multipliers (independent of
   Theorem 3.1);
+* metrics tau I + U U^T of rank r >= 2: the root of phi (Theorem 3.1) and
+  the projection vs active-set enumeration, the Woodbury inverse vs a dense
+  inverse, a zero column changes nothing, rank one through the rank-r
+  routine equals the breakpoint root;
 * the weighted prox itself vs an independent ADMM solver with dense linear
-  solves, on tiny grids, for iso/aniso TV, with and without the constraint;
+  solves, on tiny grids, for iso/aniso TV, with and without the constraint,
+  for metric ranks 0, 1 and 2;
 * with u = 0 and tau = 1 the iteration is the Beck-Teboulle fast gradient
   projection for constrained TV denoising.
 """
@@ -157,7 +162,8 @@ def _admm_wprox(v, tau, u, lam, kind, cset, iters=30000, rho=1.0):
     n = v.size
     Ds = _dense_D(shape)
     D = np.vstack(Ds)
-    B = tau * np.eye(n) + (np.outer(u.ravel(), u.ravel()) if u is not None else 0)
+    Uc = tp._cols(u, shape)
+    B = tau * np.eye(n) + Uc.T @ Uc
     M = B + rho * (D.T @ D) + rho * np.eye(n)
     Minv = np.linalg.inv(M)
     vv = v.ravel()
@@ -189,11 +195,18 @@ def _admm_wprox(v, tau, u, lam, kind, cset, iters=30000, rho=1.0):
     ("aniso", "nonneg", (3, 3, 5), 1),
     ("iso", "none", (3, 4, 3), 1),
     ("aniso", "nonneg", (4, 3, 3), 0),
+    ("iso", "nonneg", (3, 4, 4), 2),
+    ("aniso", "nonneg", (3, 3, 4), 3),
 ])
 def test_wprox_matches_admm(kind, cset, shape, rank):
     rng = np.random.default_rng(4)
     v = rng.standard_normal(shape) * 0.5 + 0.1
-    u = 0.3 * rng.standard_normal(shape) if rank else None
+    if rank == 0:
+        u = None
+    elif rank == 1:
+        u = 0.3 * rng.standard_normal(shape)
+    else:
+        u = 0.3 * rng.standard_normal((rank,) + shape)
     tau, lam = 0.7, 0.15
     x_fgp = tp.wprox(v, tau, u, lam, kind, cset, n_iter=20000)
     x_admm = _admm_wprox(v, tau, u, lam, kind, cset)
@@ -228,3 +241,73 @@ def test_unweighted_case_is_beck_teboulle():
     # the rank-one code path with u = 0 gives the same iterates
     got0 = tp.wprox(b, 1.0, np.zeros_like(b), lam, "iso", "nonneg", n_iter=K)
     assert np.max(np.abs(got0 - ref)) < 1e-14
+
+
+def _enumerate_projection(w, B):
+    """argmin_{x >= 0} 1/2 (x - w)^T B (x - w) by enumerating the free set and
+    checking the KKT multipliers (independent of Theorem 3.1)."""
+    n = w.size
+    for act in itertools.product([True, False], repeat=n):
+        S = np.array(act)
+        x = np.zeros(n)
+        if S.any():
+            x[S] = w[S] + np.linalg.solve(B[np.ix_(S, S)], B[np.ix_(S, ~S)] @ w[~S])
+        mu = (B @ (x - w))[~S]
+        if np.all(x[S] >= -1e-13) and np.all(mu >= -1e-13):
+            return x
+    raise AssertionError("no KKT point")
+
+
+@pytest.mark.parametrize("r", [2, 3, 5])
+def test_rank_r_projection_vs_active_set_enumeration(r):
+    rng = np.random.default_rng(30 + r)
+    n = 10
+    for _ in range(8):
+        w = rng.standard_normal((1, 2, 5))
+        U = rng.standard_normal((r, 1, 2, 5)) * rng.uniform(0.1, 1.5)
+        tau = float(rng.uniform(0.1, 3))
+        Uc = U.reshape(r, n)
+        B = tau * np.eye(n) + Uc.T @ Uc
+        ref = _enumerate_projection(w.ravel(), B)
+        got, beta = tp.weighted_projection_nonneg(w, tau, U)
+        assert np.max(np.abs(got.ravel() - ref)) < 1e-12
+        # KKT reading of Theorem 3.1: beta* = U^T (prox - w), and phi(beta*) = 0
+        assert np.max(np.abs(beta - Uc @ (got.ravel() - w.ravel()))) < 1e-12
+        assert np.max(np.abs(tp.phi(beta, w, tau, U))) < 1e-12
+
+
+def test_rank_r_root_consistency():
+    rng = np.random.default_rng(40)
+    shape = (6, 7, 5)
+    w = rng.standard_normal(shape)
+    u = rng.standard_normal(shape) * 0.7
+    tau = 0.4
+    # rank one through the rank-r Newton routine equals the breakpoint root
+    b1 = tp.root_phi_exact(w, tau, u)
+    br = tp.root_phi_rank(w, tau, u[None])
+    assert abs(br[0] - b1) < 1e-13 * max(1.0, abs(b1))
+    # a zero column changes nothing (its beta component is 0)
+    U2 = np.stack([u, np.zeros(shape)])
+    x2, beta2 = tp.weighted_projection_nonneg(w, tau, U2)
+    x1, _ = tp.weighted_projection_nonneg(w, tau, u)
+    assert np.max(np.abs(x2 - x1)) < 1e-13 and abs(beta2[1]) < 1e-15
+    # column order does not matter
+    U3 = rng.standard_normal((3,) + shape)
+    xa, ba = tp.weighted_projection_nonneg(w, tau, U3)
+    xb, bb = tp.weighted_projection_nonneg(w, tau, U3[::-1])
+    assert np.max(np.abs(xa - xb)) < 1e-12 and np.max(np.abs(ba - bb[::-1])) < 1e-12
+
+
+@pytest.mark.parametrize("r", [1, 2, 4])
+def test_woodbury_inverse_rank_r(r):
+    rng = np.random.default_rng(50 + r)
+    shape = (3, 4, 5)
+    n = 60
+    U = rng.standard_normal((r,) + shape)
+    y = rng.standard_normal(shape)
+    tau = 0.3
+    B = tau * np.eye(n) + U.reshape(r, n).T @ U.reshape(r, n)
+    ref = np.linalg.solve(B, y.ravel())
+    got = tp.apply_B_inv(y, tau, U)
+    assert np.max(np.abs(got.ravel() - ref)) < 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(tp.apply_B(got, tau, U) - y)) < 1e-12
