@@ -194,9 +194,10 @@ def root_phi_rank(w, tau, u, max_iter=200):
 
     phi is the gradient of the strongly convex piecewise-quadratic Psi; on
     the piece with active set A = {w - U beta / tau > 0} it is affine with
-    Jacobian H = I + U_A^T U_A / tau.  Newton steps -H^-1 phi with
-    backtracking on Psi (Armijo, factor 1/2) converge; when a full step keeps
-    the active set it lands on the root of that piece, i.e. the exact root.
+    Jacobian H = I + U_A^T U_A / tau.  The full Newton step -H^-1 phi is
+    taken when it stays on its piece: it then lands on the root of that
+    affine piece, i.e. the exact root.  Otherwise the step is shortened by
+    backtracking on Psi (Armijo, factor 1/2), which converges globally.
     """
     wf = np.ravel(w)
     U = _cols(u, np.shape(w))
@@ -208,17 +209,17 @@ def root_phi_rank(w, tau, u, max_iter=200):
         g = U @ (wf - np.maximum(z, 0.0)) + beta
         H = np.eye(r) + (U[:, A] @ U[:, A].T) / tau
         d = -np.linalg.solve(H, g)
+        full = beta + d
+        if np.array_equal(wf - U.T @ full / tau > 0, A):
+            return full
         psi0 = _psi_fn(beta, wf, tau, U)
         slope = float(g @ d)
-        if slope >= 0.0:          # g = 0 to rounding: beta is the root
-            return beta
         t = 1.0
-        while _psi_fn(beta + t * d, wf, tau, U) > psi0 + 1e-4 * t * slope and t > 1e-30:
+        while _psi_fn(beta + t * d, wf, tau, U) > psi0 + 1e-4 * t * slope:
             t *= 0.5
-        beta_new = beta + t * d
-        if t == 1.0 and np.array_equal(wf - U.T @ beta_new / tau > 0, A):
-            return beta_new
-        beta = beta_new
+            if t < 1e-20:
+                raise RuntimeError("root_phi_rank: no decrease along the Newton direction")
+        beta = beta + t * d
     raise RuntimeError("root_phi_rank did not terminate")
 
 
