@@ -188,11 +188,14 @@ typedef enum { BQ_TV_ISO = 0, BQ_TV_ANISO = 1 } bq_tv;
 typedef enum { BQ_SET_NONE = 0, BQ_SET_NONNEG = 1 } bq_set;
 
 typedef struct {
-  int newton_total;  /* semi-smooth Newton passes over all dual iterations */
+  int newton_total;  /* root-finding passes over all dual iterations        */
   int newton_max;    /* most passes in one dual iteration                   */
-  double beta_last;  /* root of Theorem 3.1's phi at the output             */
-  double phi_last;   /* |phi(beta_last)|                                    */
+  double beta_last;  /* root of Theorem 3.1's phi at the output (its first
+                        component for a metric of rank >= 2)                */
+  double phi_last;   /* max_i |phi_i(beta_last)|                            */
 } bq_prox_stats;
+
+#define BQ_PROX_MAX_RANK 8
 
 typedef struct bq_prox bq_prox;
 
@@ -202,24 +205,31 @@ bq_status bq_prox_create(int nz, int ny, int nx, int precision, void* stream, bq
 bq_status bq_prox_destroy(bq_prox* p);
 const char* bq_prox_last_error(const bq_prox* p);
 
-/* x = argmin_{x in C} 1/2 ||x - v||^2_{tau I + u u^T} + lambda TV(x)
+/* x = argmin_{x in C} 1/2 ||x - v||^2_{tau I + U U^T} + lambda TV(x)
  * (Section 4 eq. SecondProximal_WPMTV, lambda = a_k S lambda of the
  * outer iteration), by n_iter accelerated projected-gradient iterations on
  * the dual of Section 4.1 (step tau / (12 lambda), Lemma 4.1 with
  * omega_min = tau), the projection onto C by Theorem 3.1 with the
- * semi-smooth Newton root-find of Algorithm 4.3 (safeguarded), and the
- * Woodbury inverse of the metric (Section 4.3).  Output x(P_K).
+ * semi-smooth Newton root-find of Algorithm 4.3 (safeguarded: bracketing for
+ * r = 1, backtracking on the function whose gradient is phi for r >= 2),
+ * and the Woodbury inverse of the metric (Section 4.3).  Output x(P_K).
  *   v      device, image (nz*ny*nx real, precision of p)
  *   tau    > 0
- *   u      device, rank-one factor of the metric, or NULL for tau I
+ *   U      device, the r columns of the metric's low-rank factor, column c
+ *          at U + c * nz*ny*nx (precision of p); may be NULL when r = 0
+ *   r      0 <= r <= BQ_PROX_MAX_RANK (0: metric tau I)
  *   lambda > 0
  *   tv     bq_tv;  cset  bq_set;  n_iter >= 0
  *   x_out  device, image, overwritten
  *   P_io   device, 3 x image (component d = finite difference along array
  *          axis d: 0 = z, 1 = y, 2 = x) or NULL.  When given it is the
  *          starting dual point and receives P_K; NULL starts from zero.
- *   st     host or NULL */
-bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* u, double lambda, int tv,
+ *   st     host or NULL
+ * Runs on the workspace's own stream after the work pending on the stream
+ * given at creation, and returns once the result is complete.
+ * Errors: BQ_EINVAL (arguments), BQ_EDEVICE; BQ_NOTCONV if the root-find
+ * hit its pass limit in some dual iteration (x is still returned). */
+bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, double lambda, int tv,
                    int cset, int n_iter, void* x_out, void* P_io, bq_prox_stats* st);
 
 #ifdef __cplusplus

@@ -21,6 +21,7 @@ BQ_TV_ISO, BQ_TV_ANISO = 0, 1
 BQ_SET_NONE, BQ_SET_NONNEG = 0, 1
 PASS_NAMES = ("zf", "xf", "yc", "xi", "zi", "xy", "vec")
 BQ_TIMING_ALL = (1 << len(PASS_NAMES)) - 1
+BQ_PROX_MAX_RANK = 8
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
             "bq_grad", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",
@@ -76,7 +77,7 @@ def load() -> ct.CDLL:
         "bq_prox_create": ([I, I, I, I, P, ct.POINTER(P)], I),
         "bq_prox_destroy": ([P], I),
         "bq_prox_last_error": ([P], ct.c_char_p),
-        "bq_wprox": ([P, P, D, P, D, I, I, I, P, P, ct.POINTER(ProxStats)], I),
+        "bq_wprox": ([P, P, D, P, I, D, I, I, I, P, P, ct.POINTER(ProxStats)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -205,20 +205,28 @@ class WProx:
     def __call__(self, v: torch.Tensor, tau: float, u: torch.Tensor | None, lam: float,
                  tv: str = "iso", cset: str = "nonneg", n_iter: int = 50,
                  P: torch.Tensor | None = None, out: torch.Tensor | None = None):
+        """u: None (metric tau I), an image (rank one), or the r columns of
+        the metric factor as an (r,) + image-shape tensor."""
         for t in (v, u, P):
             if t is not None and (t.dtype != self.rdtype or t.device.type != "cuda"):
                 raise ValueError(f"expected {self.rdtype} cuda tensors")
         if tuple(v.shape) != self.shape:
             raise ValueError("v has the wrong shape")
-        if u is not None and tuple(u.shape) != self.shape:
-            raise ValueError("u has the wrong shape")
+        if u is None:
+            r = 0
+        elif tuple(u.shape) == self.shape:
+            r = 1
+        elif u.dim() == 4 and tuple(u.shape[1:]) == self.shape:
+            r = int(u.shape[0])
+        else:
+            raise ValueError("u must be an image or an (r,) + image-shape stack")
         if P is not None and tuple(P.shape) != (3,) + self.shape:
             raise ValueError("P must have shape (3,) + image shape")
         v = v.contiguous()
-        u = None if u is None else u.contiguous()
+        u = None if u is None or r == 0 else u.contiguous()
         x = torch.empty_like(v) if out is None else out
         st = L.ProxStats()
-        s = self._lib.bq_wprox(self._h, _ptr(v), float(tau), _ptr(u), float(lam),
+        s = self._lib.bq_wprox(self._h, _ptr(v), float(tau), _ptr(u), r, float(lam),
                                L.BQ_TV_ISO if tv == "iso" else L.BQ_TV_ANISO,
                                L.BQ_SET_NONNEG if cset == "nonneg" else L.BQ_SET_NONE,
                                int(n_iter), _ptr(x), _ptr(P), ct.byref(st))

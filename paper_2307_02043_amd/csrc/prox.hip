@@ -28,6 +28,7 @@
 
 #include "../../include/bq.h"
 #include "bq_common.h"
+#include "prox_internal.h"
 
 namespace bq {
 
@@ -333,22 +334,6 @@ __global__ void k_px_init(ProxState* st, double tau, double lam, int has_u, int 
 
 using namespace bq;
 
-struct bq_prox {
-  int nz = 0, ny = 0, nx = 0, prec = 0;
-  size_t V = 0;
-  hipStream_t stream = nullptr;  // caller's stream
-  hipStream_t own = nullptr;     // library stream (capturable), default priority
-  hipEvent_t ev = nullptr;
-  std::string err;
-  void* a = nullptr;
-  void* P = nullptr;
-  void* R = nullptr;
-  double* partial = nullptr;
-  ProxState* st = nullptr;
-  int np = 0;
-  int max_passes = 8;  // evaluations of phi per dual iteration (1 fused + 7 passes)
-};
-
 namespace {
 
 thread_local std::string g_prox_create_error;
@@ -461,7 +446,7 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
 
 void free_prox(bq_prox* p) {
   if (!p) return;
-  void* ptrs[] = {p->a, p->P, p->R, p->partial, p->st};
+  void* ptrs[] = {p->a, p->P, p->R, p->xbuf, p->partial, p->st, p->rst};
   for (void* q : ptrs) if (q) (void)hipFree(q);
   if (p->ev) (void)hipEventDestroy(p->ev);
   if (p->own) (void)hipStreamDestroy(p->own);
@@ -485,8 +470,10 @@ bq_status bq_prox_create(int nz, int ny, int nx, int precision, void* stream, bq
   const size_t es = precision == BQ_F32 ? 4 : 8;
   if (hipMalloc(&p->a, p->V * es) != hipSuccess || hipMalloc(&p->P, 3 * p->V * es) != hipSuccess ||
       hipMalloc(&p->R, 3 * p->V * es) != hipSuccess ||
-      hipMalloc((void**)&p->partial, (size_t)p->np * 4 * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&p->st, sizeof(ProxState)) != hipSuccess) {
+      hipMalloc(&p->xbuf, p->V * es) != hipSuccess ||
+      hipMalloc((void**)&p->partial, (size_t)p->np * PX_PART * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->st, sizeof(ProxState)) != hipSuccess ||
+      hipMalloc((void**)&p->rst, prox_rank_state_bytes()) != hipSuccess) {
     free_prox(p);
     g_prox_create_error = "out of device memory";
     return BQ_ENOMEM;
@@ -509,13 +496,19 @@ bq_status bq_prox_destroy(bq_prox* p) {
 
 const char* bq_prox_last_error(const bq_prox* p) { return p ? p->err.c_str() : g_prox_create_error.c_str(); }
 
-bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* u, double lambda, int tv, int cset,
-                   int n_iter, void* x_out, void* P_io, bq_prox_stats* st) {
+bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, double lambda, int tv,
+                   int cset, int n_iter, void* x_out, void* P_io, bq_prox_stats* st) {
   if (!p) return BQ_EINVAL;
   if (!v || !x_out) { p->err = "null device pointer"; return BQ_EINVAL; }
   if (!(tau > 0) || !(lambda > 0) || n_iter < 0) { p->err = "tau, lambda must be > 0 and n_iter >= 0"; return BQ_EINVAL; }
   if (tv != BQ_TV_ISO && tv != BQ_TV_ANISO) { p->err = "tv"; return BQ_EINVAL; }
   if (cset != BQ_SET_NONE && cset != BQ_SET_NONNEG) { p->err = "cset"; return BQ_EINVAL; }
+  if (r < 0 || r > BQ_PROX_MAX_RANK) { p->err = "metric rank r must be in [0, BQ_PROX_MAX_RANK]"; return BQ_EINVAL; }
+  if (r > 0 && !U) { p->err = "U is NULL with r > 0"; return BQ_EINVAL; }
+  if (r >= 2)
+    return p->prec == BQ_F32 ? run_wprox_rank<float>(p, v, tau, U, r, lambda, tv, cset, n_iter, x_out, P_io, st)
+                             : run_wprox_rank<double>(p, v, tau, U, r, lambda, tv, cset, n_iter, x_out, P_io, st);
+  const void* u = r == 1 ? U : nullptr;
   return p->prec == BQ_F32 ? run_wprox<float>(p, v, tau, u, lambda, tv, cset, n_iter, x_out, P_io, st)
                            : run_wprox<double>(p, v, tau, u, lambda, tv, cset, n_iter, x_out, P_io, st);
 }

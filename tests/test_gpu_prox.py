@@ -143,3 +143,86 @@ def test_wprox_graph_replays_are_stable(dev):
             assert torch.equal(x, first), rep
         del junk
     px.close()
+
+
+# ---- metrics tau I + U U^T of rank r >= 2 -----------------------------------
+
+def _inputs_rank(shape, r, seed):
+    rng = np.random.default_rng(seed)
+    v = 0.02 * rng.random(shape) + 0.005 * rng.standard_normal(shape)
+    U = 0.1 * rng.standard_normal((r,) + shape)
+    return v, U
+
+
+@pytest.mark.parametrize("r,tv,cset", [(2, "iso", "nonneg"), (3, "aniso", "nonneg"), (5, "iso", "nonneg"),
+                                       (8, "aniso", "nonneg"), (4, "iso", "none")])
+def test_wprox_rank_r_f64_matches_oracle(dev, r, tv, cset):
+    shape = (13, 17, 19)
+    v, U = _inputs_rank(shape, r, 100 + r)
+    ref = tp.wprox(v, 0.8, U, 2e-3, tv, cset, n_iter=30)
+    got, info, _ = _run(dev, shape, "f64", v, 0.8, U, 2e-3, tv, cset, 30)
+    assert _rel(got, ref) < 1e-10, _rel(got, ref)
+    if cset == "nonneg":
+        assert np.all(got >= 0)
+        assert info.newton_max <= 12 and info.newton_total >= 31
+
+
+def test_wprox_rank_r_f32_matches_oracle(dev):
+    shape = (20, 24, 28)
+    v, U = _inputs_rank(shape, 3, 7)
+    ref = tp.wprox(v, 1.0, U, 1e-3, "iso", "nonneg", n_iter=40)
+    got, info, _ = _run(dev, shape, "f32", v, 1.0, U, 1e-3, "iso", "nonneg", 40)
+    assert _rel(got, ref) < 2e-4, _rel(got, ref)
+
+
+def test_wprox_rank_r_projection_zero_column_and_warm_start(dev):
+    shape = (12, 14, 10)
+    v, U = _inputs_rank(shape, 3, 11)
+    # n_iter = 0: x = prox^B_C(v), Theorem 3.1 with a rank-3 factor
+    got0, _, _ = _run(dev, shape, "f64", v, 0.5, U, 1e-3, "iso", "nonneg", 0)
+    ref0, _ = tp.weighted_projection_nonneg(v, 0.5, U)
+    assert _rel(got0, ref0) < 1e-12
+    # a zero column: the rank-2 path equals the rank-one path
+    U2 = np.stack([U[0], np.zeros(shape)])
+    a, _, _ = _run(dev, shape, "f64", v, 0.5, U2, 1e-3, "iso", "nonneg", 20)
+    b, _, _ = _run(dev, shape, "f64", v, 0.5, U[0], 1e-3, "iso", "nonneg", 20)
+    assert _rel(a, b) < 1e-11
+    # dual warm start
+    x20, P20 = tp.wprox(v, 0.5, U, 1e-3, "iso", "nonneg", n_iter=20, return_dual=True)
+    ref = tp.wprox(v, 0.5, U, 1e-3, "iso", "nonneg", n_iter=15, P0=P20)
+    got20, _, Pg = _run(dev, shape, "f64", v, 0.5, U, 1e-3, "iso", "nonneg", 20, P=np.zeros((3,) + shape))
+    assert _rel(got20, x20) < 1e-10 and _rel(Pg, P20) < 1e-10
+    got, _, _ = _run(dev, shape, "f64", v, 0.5, U, 1e-3, "iso", "nonneg", 15, P=Pg)
+    assert _rel(got, ref) < 1e-10
+
+
+def test_wprox_rank_r_rejects_bad_rank_and_replays_stably(dev):
+    from paper_2307_02043_amd import WProx
+    from paper_2307_02043_amd import _lib as L
+    shape = (10, 12, 14)
+    v, U = _inputs_rank(shape, 4, 13)
+    px = WProx(shape, "f64")
+    vt = torch.from_numpy(v).to(dev)
+    Ut = torch.from_numpy(U).to(dev)
+    x = torch.empty_like(vt)
+    lib = L.load()
+    st = L.ProxStats()
+    P = L.ct.c_void_p
+    for r, Up in ((L.BQ_PROX_MAX_RANK + 1, Ut), (-1, Ut), (2, None)):
+        s = lib.bq_wprox(px._h, P(vt.data_ptr()), 0.5, None if Up is None else P(Up.data_ptr()), r, 1e-3,
+                         L.BQ_TV_ISO, L.BQ_SET_NONNEG, 5, P(x.data_ptr()), None, L.ct.byref(st))
+        assert s == L.BQ_EINVAL, r
+    ref = tp.wprox(v, 0.5, U, 1e-3, "iso", "nonneg", n_iter=25)
+    first = None
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=dev).cumsum(0)
+        torch.cuda.synchronize()
+        y, _ = px(vt, 0.5, Ut, 1e-3, "iso", "nonneg", 25)
+        torch.cuda.synchronize()
+        if first is None:
+            first = y.clone()
+            assert _rel(y.cpu().numpy(), ref) < 1e-10
+        else:
+            assert torch.equal(y, first), rep
+        del junk
+    px.close()
