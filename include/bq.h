@@ -232,6 +232,66 @@ const char* bq_prox_last_error(const bq_prox* p);
 bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, double lambda, int tv,
                    int cset, int n_iter, void* x_out, void* P_io, bq_prox_stats* st);
 
+/* ---------------------------------------------------------------------
+ * Mini-batch quasi-Newton proximal iteration (Algorithm 4.1)
+ * --------------------------------------------------------------------- */
+typedef struct {
+  int S;            /* number of subsets, 1 <= S <= BQ_PROX_MAX_RANK          */
+  double a;         /* step size a_k (constant), > 0                          */
+  double lambda;    /* TV weight lambda, > 0                                  */
+  double alpha;     /* alpha_s of Algorithm 4.1 (every subset), > 0           */
+  double gamma;     /* scaling of the initial SR1 metric (Algorithm 4.2), (0,1] */
+  double tau_max;   /* upper bound on tau of Algorithm 4.2, > 0               */
+  int tv;           /* bq_tv                                                  */
+  int cset;         /* bq_set                                                 */
+  int prox_iters;   /* dual iterations of each WPM, >= 0                      */
+} bq_qn_params;
+
+typedef struct {
+  int k;            /* iteration just completed (1-based)                     */
+  int subset;       /* s', the subset whose gradient was computed             */
+  double loss;      /* F_{s'}(x_{k-1}) = (S/L) sum_{l in s'} f_l              */
+  double tau;       /* tau_{s'} of Algorithm 4.2 after this iteration         */
+  int u_kept;       /* 1 if s' keeps its rank-one correction                  */
+  int metric_rank;  /* columns of U passed to the WPM (0 for k <= S)          */
+  double tau_sum;   /* tau of the WPM metric: alpha (k <= S) or sum_s tau_s   */
+  int prox_passes;  /* root-finding passes of the WPM                        */
+} bq_qn_info;
+
+typedef struct bq_qn bq_qn;
+
+/* Outer iteration of Algorithm 4.1 on an LS/Born context and a prox
+ * workspace of the same precision and an N x N x N image.  The S subsets
+ * are given as consecutive runs of illumination indices:
+ *   subset_idx  host, sum_s subset_len[s] indices into the context's L
+ *               illuminations; subset_len host, S positive lengths.
+ * F_s = (S/L) sum_{l in subset s} f_l (eq. NewModelPro).  Per subset the
+ * object keeps xbar_s, gbar_s and u_s (3S device images, Section 4.4) and
+ * tau_s.  ls and px are borrowed (they must outlive the object); the
+ * object owns its buffers.  Errors: BQ_EINVAL, BQ_EUNSUPPORTED (precision or
+ * shape mismatch), BQ_ENOMEM. */
+bq_status bq_qn_create(bq_ctx* ls, bq_prox* px, const bq_qn_params* prm, const int* subset_idx,
+                       const int* subset_len, bq_qn** out);
+bq_status bq_qn_destroy(bq_qn* q);
+const char* bq_qn_last_error(const bq_qn* q);
+
+/* One iteration x_{k-1} -> x_k of Algorithm 4.1 with the choices of
+ * Section 4.3 (x_s^k = x_{k-1}, g_s^k = grad F_{s'}(x_{k-1}) for every s).
+ *   x     device image, in: x_{k-1}, out: x_k
+ *   y     device, the measurements of all L illuminations, [L][N][N] complex
+ *   pick  the subset s' for k > S: -1 = strategy I (s' = k - 1 mod S), or
+ *         0..S-1 = the draw of strategy II (made by the caller); ignored for
+ *         k <= S, where s' = k - 1
+ *   info  host or NULL
+ * Steps: gradient of subset s' (bq_grad); for a revisited subset the SR1
+ * metric of Algorithm 4.2 from (x_{k-1} - xbar, g - gbar) (a subset seen
+ * once keeps alpha I); for k <= S the WPM with metric alpha I and weight
+ * a lambda of x_{k-1} - (a/alpha) g; for k > S the WPM with metric
+ * Btilde = sum_s tau_s I + U U^T (the S columns u_s, zero where dropped)
+ * and weight a S lambda of v = x_{k-1} - a S Btilde^-1 g (Woodbury).
+ * Returns the status of the solves (BQ_NOTCONV etc.) or of the WPM. */
+bq_status bq_qn_step(bq_qn* q, void* x, const void* y, int pick, bq_qn_info* info);
+
 #ifdef __cplusplus
 }
 #endif

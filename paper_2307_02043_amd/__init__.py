@@ -10,7 +10,8 @@ from ._lib import load as _load
 
 _load()
 
-from .api import BQError, LSContext, ProxInfo, SolveInfo, WProx  # noqa: E402
+from .api import BQError, LSContext, ProxInfo, QNInfo, QNIteration, SolveInfo, WProx  # noqa: E402
 from .autograd import LSData, ls_data  # noqa: E402
 
-__all__ = ["BQError", "LSContext", "LSData", "ProxInfo", "SolveInfo", "WProx", "ls_data"]
+__all__ = ["BQError", "LSContext", "LSData", "ProxInfo", "QNInfo", "QNIteration", "SolveInfo", "WProx",
+           "ls_data"]

@@ -25,7 +25,8 @@ BQ_PROX_MAX_RANK = 8
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
             "bq_grad", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",
-            "bq_prox_last_error", "bq_wprox")
+            "bq_prox_last_error", "bq_wprox", "bq_qn_create", "bq_qn_destroy", "bq_qn_last_error",
+            "bq_qn_step")
 
 
 class Geom(ct.Structure):
@@ -48,6 +49,18 @@ class SolveStats(ct.Structure):
 class ProxStats(ct.Structure):
     _fields_ = [("newton_total", ct.c_int), ("newton_max", ct.c_int),
                 ("beta_last", ct.c_double), ("phi_last", ct.c_double)]
+
+
+class QnParams(ct.Structure):
+    _fields_ = [("S", ct.c_int), ("a", ct.c_double), ("lam", ct.c_double), ("alpha", ct.c_double),
+                ("gamma", ct.c_double), ("tau_max", ct.c_double), ("tv", ct.c_int), ("cset", ct.c_int),
+                ("prox_iters", ct.c_int)]
+
+
+class QnInfo(ct.Structure):
+    _fields_ = [("k", ct.c_int), ("subset", ct.c_int), ("loss", ct.c_double), ("tau", ct.c_double),
+                ("u_kept", ct.c_int), ("metric_rank", ct.c_int), ("tau_sum", ct.c_double),
+                ("prox_passes", ct.c_int)]
 
 
 _lib = None
@@ -78,6 +91,10 @@ def load() -> ct.CDLL:
         "bq_prox_destroy": ([P], I),
         "bq_prox_last_error": ([P], ct.c_char_p),
         "bq_wprox": ([P, P, D, P, I, D, I, I, I, P, P, ct.POINTER(ProxStats)], I),
+        "bq_qn_create": ([P, P, ct.POINTER(QnParams), ct.POINTER(I), ct.POINTER(I), ct.POINTER(P)], I),
+        "bq_qn_destroy": ([P], I),
+        "bq_qn_last_error": ([P], ct.c_char_p),
+        "bq_qn_step": ([P, P, P, I, ct.POINTER(QnInfo)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

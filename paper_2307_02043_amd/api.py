@@ -233,3 +233,68 @@ class WProx:
         if s < 0:
             raise BQError(s, self._lib.bq_prox_last_error(self._h).decode())
         return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last)
+
+
+@dataclass
+class QNInfo:
+    k: int
+    subset: int
+    loss: float
+    tau: float
+    u_kept: bool
+    metric_rank: int
+    tau_sum: float
+    prox_passes: int
+
+
+class QNIteration:
+    """Outer iteration of the mini-batch quasi-Newton proximal method
+    (Algorithm 4.1, strategies I/II of Section 4.3, SR1 metrics of
+    Algorithm 4.2) over an LSContext and a WProx of the same precision."""
+
+    def __init__(self, ls: LSContext, px: WProx, subsets, a: float, lam: float, alpha: float,
+                 gamma: float = 0.8, tau_max: float = 1e8, tv: str = "iso", cset: str = "nonneg",
+                 prox_iters: int = 50):
+        self._lib = L.load()
+        self._ls, self._px = ls, px   # kept alive while this object exists
+        subsets = [list(map(int, s)) for s in subsets]
+        self.S = len(subsets)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(s, dtype=np.int32) for s in subsets]))
+        lens = np.ascontiguousarray(np.array([len(s) for s in subsets], dtype=np.int32))
+        prm = L.QnParams(self.S, float(a), float(lam), float(alpha), float(gamma), float(tau_max),
+                         L.BQ_TV_ISO if tv == "iso" else L.BQ_TV_ANISO,
+                         L.BQ_SET_NONNEG if cset == "nonneg" else L.BQ_SET_NONE, int(prox_iters))
+        h = ct.c_void_p()
+        s = self._lib.bq_qn_create(ls._h, px._h, ct.byref(prm), flat.ctypes.data_as(ct.POINTER(ct.c_int)),
+                                   lens.ctypes.data_as(ct.POINTER(ct.c_int)), ct.byref(h))
+        if s != L.BQ_OK:
+            raise BQError(s, self._lib.bq_qn_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bq_qn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, x: torch.Tensor, y: torch.Tensor, pick: int = -1) -> QNInfo:
+        """x (N^3 real, updated in place: x_{k-1} -> x_k); y: measurements
+        of all L illuminations, (L, N, N) complex; pick: -1 for strategy I,
+        else the strategy-II draw in 0..S-1."""
+        N = self._ls.N
+        if x.dtype != self._ls.rdtype or tuple(x.shape) != (N, N, N) or not x.is_contiguous():
+            raise ValueError("x must be a contiguous N^3 tensor of the context's real type")
+        if y.dtype != self._ls.cdtype or tuple(y.shape) != (self._ls.L, N, N):
+            raise ValueError("y must be (L, N, N) of the context's complex type")
+        y = y.contiguous()
+        info = L.QnInfo()
+        s = self._lib.bq_qn_step(self._h, _ptr(x), _ptr(y), int(pick), ct.byref(info))
+        if s < 0:
+            raise BQError(s, self._lib.bq_qn_last_error(self._h).decode())
+        return QNInfo(info.k, info.subset, info.loss, info.tau, bool(info.u_kept), info.metric_rank,
+                      info.tau_sum, info.prox_passes)

@@ -8,6 +8,7 @@
 
 #include "../../include/bq.h"
 #include "bq_kernels.h"
+#include "ctx_internal.h"
 
 using namespace bq;
 
@@ -31,40 +32,6 @@ struct DevBuf {
 
 }  // namespace
 
-struct bq_ctx {
-  bq_geom g{};
-  int L = 0;
-  std::vector<bq_illum> dirs;
-  hipStream_t stream = nullptr;
-  std::string err;
-  double kb = 0.0;
-  size_t V = 0;
-  size_t csz = 0;  // bytes per complex element
-  int np_mv = 0, np_vec = 0, np_det = 0;
-  int Bcap = 0;
-  // device memory
-  void* ghat = nullptr;
-  void* twN = nullptr;
-  void* twH = nullptr;
-  void* f[8] = {};  // u w r rhat p v s t
-  void* zh = nullptr;
-  void* xh = nullptr;
-  void* rdet = nullptr;
-  C<double>* inc = nullptr;
-  SysState* state = nullptr;
-  double* part_mv = nullptr;
-  double* part_vec = nullptr;
-  double* part_det = nullptr;
-  // pinned host staging (hipHostMalloc), sized with the batch capacity
-  SysState* hstate = nullptr;
-  C<double>* hinc = nullptr;
-  double* hpart = nullptr;
-  PassTimer timer;
-  // iterations the previous batched forward / adjoint solve took: the next
-  // solve checks for convergence first after that many iterations, then
-  // after every iteration (0: no history, check every 4)
-  int hint[2] = {0, 0};
-};
 
 namespace {
 
