@@ -90,18 +90,21 @@ def copy_calibration(dev, mib):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ls_grad_128cubed_b16_f32_hbm_traffic.txt")
 
 
+# sources that define the z/y register kernels, their launch and their
+# build flags (the kernels the traffic counters are reported for)
+TRAFFIC_SOURCES = ("paper_2307_02043_amd/csrc/green_reg.hip", "paper_2307_02043_amd/csrc/bq_common.h",
+                   "paper_2307_02043_amd/csrc/bq_state.h", "paper_2307_02043_amd/csrc/bq_kernels.h",
+                   "paper_2307_02043_amd/build_lib.py")
+
+
 def source_digest():
-    """SHA-256 over the HIP sources and the C header, to tell whether the
-    kernels are still those the traffic counters were taken on."""
+    """SHA-256 over the sources of the measured kernels, to tell whether
+    they are still those the traffic counters were taken on."""
     import hashlib
     hs = hashlib.sha256()
-    cs = os.path.join(ROOT, "paper_2307_02043_amd", "csrc")
-    files = sorted(f for f in os.listdir(cs) if f.endswith((".hip", ".h")))
-    for f in files:
-        with open(os.path.join(cs, f), "rb") as fh:
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             hs.update(f.encode() + b"\0" + fh.read())
-    with open(os.path.join(ROOT, "include", "bq.h"), "rb") as fh:
-        hs.update(fh.read())
     return hs.hexdigest()
 
 
@@ -144,6 +147,8 @@ def main():
                     help="BiCGSTAB iterations of the oracle sample (0: skip)")
     ap.add_argument("--prox-workload", default="c5_ls256_f32",
                     help="workload whose weighted prox is timed alongside ('' to skip)")
+    ap.add_argument("--qn-iters", type=int, default=9,
+                    help="outer iterations of the quasi-Newton method timed alongside (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of this many MiB (reference for the "
                          "HBM traffic counters)")
@@ -329,6 +334,11 @@ def main():
                           f"3 extra applications of G")}
         log(f"oracle: {t_iter:.2f} s per BiCGSTAB iteration")
 
+    # ---- outer iteration of the method on the same workload -----------------
+    qn = None
+    if args.qn_iters > 0:
+        qn = bench_qn(w, dev, xt, dirs, args.qn_iters, 1e3 * elapsed / args.steps)
+
     # ---- weighted TV prox (second kernel of the method) ---------------------
     prox = None
     if args.prox_workload:
@@ -361,8 +371,67 @@ def main():
                    "bicgstab_iters_per_s": round(iters / elapsed, 1), "setup_s": round(setup_s, 2)},
         "passes_ms_per_step": {k: round(v / breakdown_steps, 3) for k, v in warm_ms.items()},
         "prox": prox,
+        "qn": qn,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):
+    """Outer iterations of Algorithm 4.1 (strategy I, SR1 metrics of
+    Algorithm 4.2) on the workload's grid: S subsets of B illuminations
+    (the first S B directions), x_0 = 0.5 x_true, step 1/20, gamma 0.8,
+    tau_max 1e8, 50 dual iterations per WPM, FP32.  Measurements from the
+    library's FP32 forward model (tol 1e-6) without noise."""
+    import torch
+
+    from paper_2307_02043_amd import LSContext, QNIteration, WProx
+
+    N, B = w.N, w.B
+    subsets = [list(range(s * B, (s + 1) * B)) for s in range(S)]
+    ls = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=1e-6, max_iter=w.max_iter)
+    xtt = torch.from_numpy(xt).to(dev, torch.float32)
+    y = torch.zeros((w.L, N, N), dtype=torch.complex64, device=dev)
+    for sub in subsets:
+        y[sub] = ls.forward(xtt, sub)[0]
+    ls.close()
+    ls = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol, max_iter=w.max_iter)
+    x = (0.5 * xtt).contiguous()
+    g0, _, _ = ls.grad(x, y[subsets[0]], subsets[0], S / w.L)
+    alpha = float(g0.abs().max()) / float(xtt.max())
+    lam = 1.0 / N ** 3
+    px = WProx((N, N, N), "f32")
+    qn = QNIteration(ls, px, subsets, 1.0 / 20, lam, alpha, 0.8, 1e8, prox_iters=50)
+    torch.cuda.synchronize()
+    times, infos = [], []
+    for _ in range(iters):
+        t = time.perf_counter()
+        infos.append(qn.step(x, y))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    qn.close()
+    # the rank-S WPM alone (same shape, metric rank, weight and iterations)
+    U = 0.1 * torch.randn((S, N, N, N), dtype=torch.float32, device=dev)
+    px(x, 1.0, U, lam, "iso", "nonneg", 50)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    px(x, 1.0, U, lam, "iso", "nonneg", 50)
+    torch.cuda.synchronize()
+    prox_ms = (time.perf_counter() - t) * 1e3
+    px.close()
+    ls.close()
+    first = [t for t, inf in zip(times, infos) if inf.k <= S]
+    later = [t for t, inf in zip(times, infos) if inf.k > S]
+    log(f"qn: {iters} outer iterations, {np.mean(times) * 1e3:.1f} ms each; rank-{S} WPM {prox_ms:.1f} ms")
+    return {"workload": (f"{w.name} outer iteration: {N}^3, S = {S} subsets of {B} illuminations, "
+                         f"strategy I, SR1 metrics, 50 dual iterations per WPM, FP32"),
+            "iterations": iters,
+            "ms_per_iter": round(float(np.mean(times)) * 1e3, 2),
+            "ms_per_iter_first_S": round(float(np.mean(first)) * 1e3, 2) if first else None,
+            "ms_per_iter_after_S": round(float(np.mean(later)) * 1e3, 2) if later else None,
+            "gradient_ms_same_batch": round(grad_ms, 2),
+            "rank_S_wprox_ms": round(prox_ms, 2),
+            "u_kept": sum(int(i.u_kept) for i in infos),
+            "loss_first_last": [infos[0].loss, infos[-1].loss]}
 
 
 def bench_prox(w, dev, reps=2):

@@ -70,13 +70,6 @@ struct ProxArgs {
   int iso;
 };
 
-__device__ inline void px_coords(size_t i, int ny, int nx, int& z, int& y, int& x) {
-  x = (int)(i % nx);
-  const size_t r = i / nx;
-  y = (int)(r % ny);
-  z = (int)(r / ny);
-}
-
 template <typename T>
 __device__ inline T xval(const ProxArgs<T>& a, size_t i, T theta, bool nonneg, bool has_u) {
   const T av = a.a[i];
@@ -93,29 +86,34 @@ __global__ void __launch_bounds__(PX_WG) k_div(ProxArgs<T> p) {
   const T theta0 = (T)s.theta;
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < V; i += (size_t)gridDim.x * PX_WG) {
-    int z, y, x;
-    px_coords(i, p.ny, p.nx, z, y, x);
-    const T* Rz = p.R;
-    const T* Ry = p.R + V;
-    const T* Rx = p.R + 2 * V;
-    T d = 0;
-    // (D^a)^T q at i: q[i - e_a] (if i_a > 0) - q[i] (if i_a < n_a - 1)
-    if (z > 0) d += Rz[i - sz];
-    if (z < p.nz - 1) d -= Rz[i];
-    if (y > 0) d += Ry[i - sy];
-    if (y < p.ny - 1) d -= Ry[i];
-    if (x > 0) d += Rx[i - 1];
-    if (x < p.nx - 1) d -= Rx[i];
-    const T av = p.v[i] - (T)lt * d;
-    p.a[i] = av;
-    if (s.has_u) {
-      const T uv = p.u[i];
-      acc[0] += (double)uv * d;
-      acc[1] += (double)uv * av;
-      if (av - uv * theta0 > T(0)) {
-        acc[2] += (double)uv * uv;
-        acc[3] += (double)uv * av;
+  const T* Rz = p.R;
+  const T* Ry = p.R + V;
+  const T* Rx = p.R + 2 * V;
+  // rows (z, y) over workgroups, x over threads: one division per row
+  const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
+  for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x) {
+    const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
+    const size_t base = (size_t)row * p.nx;
+    for (int x = threadIdx.x; x < p.nx; x += PX_WG) {
+      const size_t i = base + x;
+      T d = 0;
+      // (D^a)^T q at i: q[i - e_a] (if i_a > 0) - q[i] (if i_a < n_a - 1)
+      if (z > 0) d += Rz[i - sz];
+      if (z < p.nz - 1) d -= Rz[i];
+      if (y > 0) d += Ry[i - sy];
+      if (y < p.ny - 1) d -= Ry[i];
+      if (x > 0) d += Rx[i - 1];
+      if (x < p.nx - 1) d -= Rx[i];
+      const T av = p.v[i] - (T)lt * d;
+      p.a[i] = av;
+      if (s.has_u) {
+        const T uv = p.u[i];
+        acc[0] += (double)uv * d;
+        acc[1] += (double)uv * av;
+        if (av - uv * theta0 > T(0)) {
+          acc[2] += (double)uv * uv;
+          acc[3] += (double)uv * av;
+        }
       }
     }
   }
@@ -272,32 +270,36 @@ __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
   const T theta = (T)stp->theta;
   const T sig = (T)p.sigma, mom = (T)stp->mom;
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
-  for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < V; i += (size_t)gridDim.x * PX_WG) {
-    int z, y, x;
-    px_coords(i, p.ny, p.nx, z, y, x);
-    const T xc = xval(p, i, theta, nonneg, has_u);
-    const T gz = (z < p.nz - 1) ? xval(p, i + sz, theta, nonneg, has_u) - xc : T(0);
-    const T gy = (y < p.ny - 1) ? xval(p, i + sy, theta, nonneg, has_u) - xc : T(0);
-    const T gx = (x < p.nx - 1) ? xval(p, i + 1, theta, nonneg, has_u) - xc : T(0);
-    T qz = p.R[i] + sig * gz;
-    T qy = p.R[V + i] + sig * gy;
-    T qx = p.R[2 * V + i] + sig * gx;
-    if (p.iso) {
-      const T n = sqrt(qz * qz + qy * qy + qx * qx);
-      if (n > T(1)) {
-        const T inv = T(1) / n;
-        qz *= inv; qy *= inv; qx *= inv;
+  const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
+  for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x) {
+    const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
+    const size_t base = (size_t)row * p.nx;
+    for (int x = threadIdx.x; x < p.nx; x += PX_WG) {
+      const size_t i = base + x;
+      const T xc = xval(p, i, theta, nonneg, has_u);
+      const T gz = (z < p.nz - 1) ? xval(p, i + sz, theta, nonneg, has_u) - xc : T(0);
+      const T gy = (y < p.ny - 1) ? xval(p, i + sy, theta, nonneg, has_u) - xc : T(0);
+      const T gx = (x < p.nx - 1) ? xval(p, i + 1, theta, nonneg, has_u) - xc : T(0);
+      T qz = p.R[i] + sig * gz;
+      T qy = p.R[V + i] + sig * gy;
+      T qx = p.R[2 * V + i] + sig * gx;
+      if (p.iso) {
+        const T n = sqrt(qz * qz + qy * qy + qx * qx);
+        if (n > T(1)) {
+          const T inv = T(1) / n;
+          qz *= inv; qy *= inv; qx *= inv;
+        }
+      } else {
+        qz = fmin(fmax(qz, T(-1)), T(1));
+        qy = fmin(fmax(qy, T(-1)), T(1));
+        qx = fmin(fmax(qx, T(-1)), T(1));
       }
-    } else {
-      qz = fmin(fmax(qz, T(-1)), T(1));
-      qy = fmin(fmax(qy, T(-1)), T(1));
-      qx = fmin(fmax(qx, T(-1)), T(1));
+      const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
+      p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
+      p.R[i] = qz + mom * (qz - oz);
+      p.R[V + i] = qy + mom * (qy - oy);
+      p.R[2 * V + i] = qx + mom * (qx - ox);
     }
-    const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
-    p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
-    p.R[i] = qz + mom * (qz - oz);
-    p.R[V + i] = qy + mom * (qy - oy);
-    p.R[2 * V + i] = qx + mom * (qx - ox);
   }
 }
 
