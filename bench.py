@@ -377,11 +377,13 @@ def main():
 
 
 def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):
-    """Outer iterations of Algorithm 4.1 (strategy I, SR1 metrics of
-    Algorithm 4.2) on the workload's grid: S subsets of B illuminations
-    (the first S B directions), x_0 = 0.5 x_true, step 1/20, gamma 0.8,
-    tau_max 1e8, 50 dual iterations per WPM, FP32.  Measurements from the
-    library's FP32 forward model (tol 1e-6) without noise."""
+    """Outer iterations of Algorithm 4.1 (strategy I) on the workload's grid:
+    S subsets of B illuminations (the first S B directions), x_0 = 0.5
+    x_true, step 1/20, 50 dual iterations per WPM, FP32; three variants:
+    SR1 metrics of Algorithm 4.2 (gamma 0.8, tau_max 1e8) with cold solves,
+    the same with warm-started solves, and the first-order (alpha I)
+    variant with warm-started solves.  Measurements from the library's FP32
+    forward model (tol 1e-6) without noise."""
     import torch
 
     from paper_2307_02043_amd import LSContext, QNIteration, WProx
@@ -400,15 +402,25 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):
     alpha = float(g0.abs().max()) / float(xtt.max())
     lam = 1.0 / N ** 3
     px = WProx((N, N, N), "f32")
-    qn = QNIteration(ls, px, subsets, 1.0 / 20, lam, alpha, 0.8, 1e8, prox_iters=50)
-    torch.cuda.synchronize()
-    times, infos = [], []
-    for _ in range(iters):
-        t = time.perf_counter()
-        infos.append(qn.step(x, y))
+    variants = {}
+    for name, warm, fo in (("sr1", False, False), ("sr1_warm", True, False), ("first_order_warm", True, True)):
+        qn = QNIteration(ls, px, subsets, 1.0 / 20, lam, alpha, 0.8, 1e8, prox_iters=50, warm_start=warm,
+                         first_order=fo)
+        xk = x.clone()
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t)
-    qn.close()
+        times, infos = [], []
+        for _ in range(iters):
+            t = time.perf_counter()
+            infos.append(qn.step(xk, y))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        qn.close()
+        later = [t for t, inf in zip(times, infos) if inf.k > S]
+        variants[name] = {"ms_per_iter": round(float(np.mean(times)) * 1e3, 2),
+                          "ms_per_iter_after_S": round(float(np.mean(later)) * 1e3, 2) if later else None,
+                          "loss_first_last": [infos[0].loss, infos[-1].loss],
+                          "u_kept": sum(int(i.u_kept) for i in infos)}
+        log(f"qn {name}: {iters} outer iterations, {np.mean(times) * 1e3:.1f} ms each")
     # the rank-S WPM alone (same shape, metric rank, weight and iterations)
     U = 0.1 * torch.randn((S, N, N, N), dtype=torch.float32, device=dev)
     px(x, 1.0, U, lam, "iso", "nonneg", 50)
@@ -419,19 +431,13 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):
     prox_ms = (time.perf_counter() - t) * 1e3
     px.close()
     ls.close()
-    first = [t for t, inf in zip(times, infos) if inf.k <= S]
-    later = [t for t, inf in zip(times, infos) if inf.k > S]
-    log(f"qn: {iters} outer iterations, {np.mean(times) * 1e3:.1f} ms each; rank-{S} WPM {prox_ms:.1f} ms")
+    log(f"qn: rank-{S} WPM alone {prox_ms:.1f} ms")
     return {"workload": (f"{w.name} outer iteration: {N}^3, S = {S} subsets of {B} illuminations, "
-                         f"strategy I, SR1 metrics, 50 dual iterations per WPM, FP32"),
+                         f"strategy I, 50 dual iterations per WPM, FP32"),
             "iterations": iters,
-            "ms_per_iter": round(float(np.mean(times)) * 1e3, 2),
-            "ms_per_iter_first_S": round(float(np.mean(first)) * 1e3, 2) if first else None,
-            "ms_per_iter_after_S": round(float(np.mean(later)) * 1e3, 2) if later else None,
+            "variants": variants,
             "gradient_ms_same_batch": round(grad_ms, 2),
-            "rank_S_wprox_ms": round(prox_ms, 2),
-            "u_kept": sum(int(i.u_kept) for i in infos),
-            "loss_first_last": [infos[0].loss, infos[-1].loss]}
+            "rank_S_wprox_ms": round(prox_ms, 2)}
 
 
 def bench_prox(w, dev, reps=2):

@@ -144,6 +144,19 @@ bq_status bq_fields(bq_ctx* ctx, const void* x, const int* idx, int B, void* u_o
 bq_status bq_grad(bq_ctx* ctx, const void* x, const void* y, const int* idx, int B, double scale,
                   void* g_out, double* loss, bq_solve_stats* st);
 
+/* bq_grad with the fields kept and, optionally, used as starting points
+ * (warm start across outer iterations; LS model only).
+ *   u_io, w_io  device, B x N^3 complex each (context precision), aligned
+ *               with idx.  On return they hold the forward fields u_b and the
+ *               conjugated adjoint fields w_b of the batch.
+ *   start       0: the solves start from their right-hand sides (as bq_grad);
+ *               otherwise from u_io and w_io (BiCGSTAB with r0 = b - A e0; a
+ *               system whose right-hand side is zero returns zero).
+ * Other arguments, results and errors as bq_grad; BQ_EUNSUPPORTED for the
+ * Born model. */
+bq_status bq_grad_ws(bq_ctx* ctx, const void* x, const void* y, const int* idx, int B, double scale,
+                     void* g_out, double* loss, bq_solve_stats* st, void* u_io, void* w_io, int start);
+
 /* Mini-batch loss only: *loss = scale * sum_b 1/2 ||S(u_b - u_in,b) - y_b||^2
  * (forward solves and detector residual, no adjoint solve).  Arguments as
  * for bq_grad.  Used by differentiation wrappers whose backward pass calls
@@ -245,6 +258,11 @@ typedef struct {
   int tv;           /* bq_tv                                                  */
   int cset;         /* bq_set                                                 */
   int prox_iters;   /* dual iterations of each WPM, >= 0                      */
+  int warm_start;   /* nonzero: keep each subset's forward and adjoint fields
+                       and start its next solves from them (bq_grad_ws; LS
+                       model; 2 x sum_s |subset s| device fields)            */
+  int first_order;  /* nonzero: metric alpha I and weight a lambda at every
+                       iteration (no SR1): the proximal-gradient baseline   */
 } bq_qn_params;
 
 typedef struct {

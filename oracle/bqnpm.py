@@ -22,7 +22,8 @@ Readings (the paper is silent or its listing is ambiguous):
   tau* = sum_s tau_s and U = [u_1 .. u_S] (zero columns kept), and the WPM
   of step 11 has weight a S lambda;
 * the first S iterations (step 6) take the WPM with metric alpha_s I and
-  weight a lambda of v = x_{k-1} - a g / alpha_s.
+  weight a lambda of v = x_{k-1} - a g / alpha_s; the first-order variant
+  (a proximal stochastic-gradient baseline) takes that step at every k.
 
 Algorithm 4.2 is implemented as listed.  Note that its initial
 tau = <m,m> / (gamma <s,m>) with gamma <= 1 gives, by Cauchy-Schwarz,
@@ -73,6 +74,7 @@ class BQNPMParams:
     tv: str = "iso"
     cset: str = "nonneg"
     prox_iters: int = 50
+    first_order: bool = False   # metric alpha I at every iteration (no SR1)
 
 
 @dataclass
@@ -113,11 +115,11 @@ class BQNPM:
         sp = self.pick(k, draw)
         g = self.grad(sp, x)
         sub = self.subsets[sp]
-        if sub.xbar is not None and not np.array_equal(sub.xbar, x):
+        if not p.first_order and sub.xbar is not None and not np.array_equal(sub.xbar, x):
             tau, u = sr1(x - sub.xbar, g - sub.gbar, p.gamma, p.alpha, p.tau_max)
             sub.tau, sub.u = tau, (None if u is None else u.reshape(x.shape))
         sub.xbar, sub.gbar = x.copy(), g.copy()
-        if k <= p.S:
+        if k <= p.S or p.first_order:
             v = x - p.a * g / p.alpha
             xn = tvprox.wprox(v, p.alpha, None, p.a * p.lam, p.tv, p.cset, n_iter=p.prox_iters)
             return xn, sp, (sub.tau, sub.u)

@@ -138,13 +138,13 @@ class LSModel:
         return out
 
     # solves ----------------------------------------------------------------
-    def solve_forward(self, x, uin, tol, max_iter):
-        """(I - G diag(x)) u = u_in, started from u_in."""
-        return bicgstab(lambda e: e - self.G(x * e), uin, uin, tol, max_iter)
+    def solve_forward(self, x, uin, tol, max_iter, e0=None):
+        """(I - G diag(x)) u = u_in, started from u_in (or from e0)."""
+        return bicgstab(lambda e: e - self.G(x * e), uin, uin if e0 is None else e0, tol, max_iter)
 
-    def solve_adjoint(self, x, z, tol, max_iter):
-        """(I - G^H diag(x)) w = z, started from z."""
-        return bicgstab(lambda e: e - self.GH(x * e), z, z, tol, max_iter)
+    def solve_adjoint(self, x, z, tol, max_iter, e0=None):
+        """(I - G^H diag(x)) w = z, started from z (or from e0)."""
+        return bicgstab(lambda e: e - self.GH(x * e), z, z if e0 is None else e0, tol, max_iter)
 
     # model -----------------------------------------------------------------
     def forward(self, x, directions, idx, tol, max_iter, model="ls"):
@@ -161,24 +161,30 @@ class LSModel:
             stats.append((it, st, res))
         return np.stack(ys), stats
 
-    def grad(self, x, y, directions, idx, scale, tol, max_iter, model="ls"):
+    def grad(self, x, y, directions, idx, scale, tol, max_iter, model="ls", starts=None,
+             return_fields=False):
         """scale * sum_l grad f_l(x) and scale * sum_l f_l(x) over the batch.
 
-        y[b] is the measurement of illumination idx[b].  Returns
-        (g, loss, stats) with stats[b] = (it_fwd, it_adj, status_fwd,
-        status_adj).
+        y[b] is the measurement of illumination idx[b].  starts: None, or
+        per batch element a pair (u0, w0) of starting points for the forward
+        and adjoint solves (warm start, e.g. the fields of an earlier outer
+        iteration).  Returns (g, loss, stats) with stats[b] = (it_fwd,
+        it_adj, status_fwd, status_adj), and the fields [(u_b, w_b)] as a
+        fourth element when return_fields is set.
         """
         g = np.zeros(x.shape)
         loss = 0.0
         stats = []
+        fields = []
         for b, l in enumerate(idx):
             uin = incident_field(self.geom, directions[l])
+            u0, w0 = (None, None) if starts is None else starts[b]
             if model == "born":
                 u = uin
                 H = self.detector(self.G(x * uin))
                 itf, stf = 0, CONVERGED
             else:
-                u, itf, stf, _ = self.solve_forward(x, uin, tol, max_iter)
+                u, itf, stf, _ = self.solve_forward(x, uin, tol, max_iter, e0=u0)
                 H = self.detector(u - uin)
             r = H - y[b]
             loss += 0.5 * np.vdot(r, r).real
@@ -186,9 +192,12 @@ class LSModel:
             if model == "born":
                 w, ita, sta = z, 0, CONVERGED
             else:
-                w, ita, sta, _ = self.solve_adjoint(x, z, tol, max_iter)
+                w, ita, sta, _ = self.solve_adjoint(x, z, tol, max_iter, e0=w0)
             g += np.real(np.conj(u) * w)
             stats.append((itf, ita, stf, sta))
+            fields.append((u, w))
+        if return_fields:
+            return scale * g, scale * loss, stats, fields
         return scale * g, scale * loss, stats
 
     def tangent(self, x, direction, dx, tol, max_iter):

@@ -24,7 +24,7 @@ BQ_TIMING_ALL = (1 << len(PASS_NAMES)) - 1
 BQ_PROX_MAX_RANK = 8
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
-            "bq_grad", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",
+            "bq_grad", "bq_grad_ws", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_prox_create", "bq_prox_destroy",
             "bq_prox_last_error", "bq_wprox", "bq_qn_create", "bq_qn_destroy", "bq_qn_last_error",
             "bq_qn_step")
 
@@ -54,7 +54,7 @@ class ProxStats(ct.Structure):
 class QnParams(ct.Structure):
     _fields_ = [("S", ct.c_int), ("a", ct.c_double), ("lam", ct.c_double), ("alpha", ct.c_double),
                 ("gamma", ct.c_double), ("tau_max", ct.c_double), ("tv", ct.c_int), ("cset", ct.c_int),
-                ("prox_iters", ct.c_int)]
+                ("prox_iters", ct.c_int), ("warm_start", ct.c_int), ("first_order", ct.c_int)]
 
 
 class QnInfo(ct.Structure):
@@ -86,6 +86,7 @@ def load() -> ct.CDLL:
         "bq_forward": ([P, P, ct.POINTER(I), I, P, ct.POINTER(SolveStats)], I),
         "bq_fields": ([P, P, ct.POINTER(I), I, P, ct.POINTER(SolveStats)], I),
         "bq_grad": ([P, P, P, ct.POINTER(I), I, D, P, ct.POINTER(D), ct.POINTER(SolveStats)], I),
+        "bq_grad_ws": ([P, P, P, ct.POINTER(I), I, D, P, ct.POINTER(D), ct.POINTER(SolveStats), P, P, I], I),
         "bq_loss": ([P, P, P, ct.POINTER(I), I, D, ct.POINTER(D), ct.POINTER(SolveStats)], I),
         "bq_green_apply": ([P, P, P, I, I], I),
         "bq_timing": ([P, I], I),

@@ -147,6 +147,24 @@ class LSContext:
                                           _ptr(g), ct.byref(loss), st))
         return g, loss.value, _stats(st, B, s)
 
+    def grad_ws(self, x: torch.Tensor, y: torch.Tensor, idx, scale: float, u: torch.Tensor,
+                w: torch.Tensor, start: bool, out: torch.Tensor | None = None):
+        """grad with the fields kept in u, w ((B, N, N, N) complex) and, when
+        start is set, used as the starting points of the solves."""
+        N = self.N
+        x = self._real(x, (N, N, N))
+        a, pidx, B = self._idx(idx)
+        y = self._cplx(y, (B, N, N))
+        for f in (u, w):
+            if f.dtype != self.cdtype or tuple(f.shape) != (B, N, N, N) or not f.is_contiguous():
+                raise ValueError("u, w must be contiguous (B, N, N, N) tensors of the context's complex type")
+        g = torch.empty((N, N, N), dtype=self.rdtype, device=x.device) if out is None else out
+        loss = ct.c_double(0.0)
+        st = (L.SolveStats * B)()
+        s = self._check(self._lib.bq_grad_ws(self._h, _ptr(x), _ptr(y), pidx, B, float(scale), _ptr(g),
+                                             ct.byref(loss), st, _ptr(u), _ptr(w), int(bool(start))))
+        return g, loss.value, _stats(st, B, s)
+
     def loss(self, x: torch.Tensor, y: torch.Tensor, idx, scale: float):
         N = self.N
         x = self._real(x, (N, N, N))
@@ -254,7 +272,7 @@ class QNIteration:
 
     def __init__(self, ls: LSContext, px: WProx, subsets, a: float, lam: float, alpha: float,
                  gamma: float = 0.8, tau_max: float = 1e8, tv: str = "iso", cset: str = "nonneg",
-                 prox_iters: int = 50):
+                 prox_iters: int = 50, warm_start: bool = False, first_order: bool = False):
         self._lib = L.load()
         self._ls, self._px = ls, px   # kept alive while this object exists
         subsets = [list(map(int, s)) for s in subsets]
@@ -263,7 +281,8 @@ class QNIteration:
         lens = np.ascontiguousarray(np.array([len(s) for s in subsets], dtype=np.int32))
         prm = L.QnParams(self.S, float(a), float(lam), float(alpha), float(gamma), float(tau_max),
                          L.BQ_TV_ISO if tv == "iso" else L.BQ_TV_ANISO,
-                         L.BQ_SET_NONNEG if cset == "nonneg" else L.BQ_SET_NONE, int(prox_iters))
+                         L.BQ_SET_NONNEG if cset == "nonneg" else L.BQ_SET_NONE, int(prox_iters),
+                         int(bool(warm_start)), int(bool(first_order)))
         h = ct.c_void_p()
         s = self._lib.bq_qn_create(ls._h, px._h, ct.byref(prm), flat.ctypes.data_as(ct.POINTER(ct.c_int)),
                                    lens.ctypes.data_as(ct.POINTER(ct.c_int)), ct.byref(h))

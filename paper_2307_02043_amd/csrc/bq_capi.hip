@@ -153,31 +153,42 @@ bq_status check_launch(bq_ctx* c, const char* where) {
 // BiCGSTAB for B systems (I - G diag(x)) e_b = b_b.
 //   fwd:  b = u_in (generated), e = u_in on entry (written here)
 //   !fwd: b = e on entry (already computed)
+// warm: e holds the starting point on entry (otherwise the solve starts from
+// b); bvec is the adjoint right-hand side when warm (b = e on entry when cold).
 template <typename T>
-bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, bool fwd, bool plain) {
+bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, bool fwd, bool plain,
+                   bool warm = false, const C<T>* bvec = nullptr) {
   const int N = c->g.N;
   PassArgs<T> a = pass_args<T>(c, B, inc);
   VecArgs<T> va = vec_args<T>(c, B, 0, e);
   a.xpot = x;
-  // r0 = b - A e0 = G(x . e0) with e0 = b; rhat = r0
+  // cold: r0 = b - A e0 = G(x . e0) with e0 = b;  warm: r0 = b - e0 + G(x . e0);  rhat = r0
   double bfix = 0.0;
   const double* part_b = nullptr;
   if (fwd) {
-    vec_fill_incident<T>(B, N, inc, (C<T>*)e, c->stream);
-    a.zf_mode = ZF_XUIN;
+    if (warm) {
+      a.zf_mode = ZF_XV;
+      a.vin = (const C<T>*)e;
+    } else {
+      vec_fill_incident<T>(B, N, inc, (C<T>*)e, c->stream);
+      a.zf_mode = ZF_XUIN;
+    }
     bfix = (double)c->V;  // |u_in| = 1 at every voxel
   } else {
-    vec_norm<T>(va, (const C<T>*)e, c->stream);
+    vec_norm<T>(va, warm ? bvec : (const C<T>*)e, c->stream);
     part_b = c->part_vec;
     a.zf_mode = ZF_XV;
     a.vin = (const C<T>*)e;
   }
-  a.zi_mode = ZI_G_NORM;
+  a.zi_mode = warm ? ZI_RES_NORM : ZI_G_NORM;
+  a.vz = (const C<T>*)e;
+  a.bsrc = fwd ? nullptr : bvec;
   a.out = va.r;
   a.out2 = va.rhat;
   a.mask = RUN_ALL;
   if (green_apply<T>(a, c->stream, &c->timer)) return check_launch(c, "green_apply(init)");
   sc_init(B, c->state, c->part_mv, c->np_mv, part_b, c->np_vec, bfix, c->g.tol, c->g.max_iter, c->stream);
+  if (warm) vec_zero_if_b0<T>(B, c->V, c->state, (C<T>*)e, c->stream);  // b = 0: the solution is 0
   // The scalar step that tests convergence and forms beta closes each pass
   // (and is issued once here for the first), so that a host check right
   // after a pass already sees its outcome.
@@ -387,11 +398,18 @@ bq_status do_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   return summarize(c, stats);
 }
 
+// u_io / w_io (optional, B x N^3 complex each): receive the forward and
+// adjoint fields; with start != 0 they are also the starting points of the
+// solves (warm start).
 template <typename T>
 bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, void* g,
-                  double* loss, bq_solve_stats* st) {
+                  double* loss, bq_solve_stats* st, void* u_io = nullptr, void* w_io = nullptr, int start = 0) {
   if (bq_status s = check_batch(c, idx, B)) return s;
   if (!x || !y || !g) return set_err(c, BQ_EINVAL, "null device pointer");
+  const bool ws = u_io != nullptr;
+  if (ws && (!w_io || c->g.model != BQ_MODEL_LS))
+    return set_err(c, ws && !w_io ? BQ_EINVAL : BQ_EUNSUPPORTED,
+                   "field buffers: both u_io and w_io, LS model only");
   const bool plain = (c->g.flags & BQ_FLAG_PLAIN) != 0;
   if (bq_status s = ensure_capacity(c, plain ? 1 : B)) return s;
   std::vector<bq_solve_stats> stats(B);
@@ -417,30 +435,37 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
       sub = 0;
       for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
     } else {
-      if (bq_status s = bicgstab<T>(c, nb, (const T*)x, c->f[F_U], c->inc, true, plain)) return s;
-      field = (const C<T>*)c->f[F_U];
+      void* ue = ws ? (void*)((C<T>*)u_io + (size_t)b0 * c->V) : c->f[F_U];
+      if (bq_status s = bicgstab<T>(c, nb, (const T*)x, ue, c->inc, true, plain, ws && start)) return s;
+      field = (const C<T>*)ue;
       sub = 1;
     }
     record(c, stats, b0, nb, true, 1);
     detector<T>(nb, N, field, sub, c->inc, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det,
                 c->np_det, c->stream);
-    // adjoint right-hand side (conjugated): G S^T conj(r)
+    // adjoint right-hand side (conjugated): G S^T conj(r); for a warm start
+    // it goes to the p buffer (free until the first iteration) and the solve
+    // starts from w_io
+    const bool warm_adj = ws && start;
+    void* we = ws ? (void*)((C<T>*)w_io + (size_t)b0 * c->V) : c->f[F_W];
     {
       PassArgs<T> a = pass_args<T>(c, nb, c->inc);
       a.rdet = (const C<T>*)c->rdet;
       a.zf_mode = ZF_DETCONJ;
       a.zi_mode = ZI_G;
-      a.out = (C<T>*)c->f[F_W];
+      a.out = warm_adj ? (C<T>*)c->f[F_P] : (C<T>*)we;
       if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
     }
     if (born) {
       for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
     } else {
-      if (bq_status s = bicgstab<T>(c, nb, (const T*)x, c->f[F_W], c->inc, false, plain)) return s;
+      if (bq_status s = bicgstab<T>(c, nb, (const T*)x, we, c->inc, false, plain, warm_adj,
+                                    (const C<T>*)c->f[F_P]))
+        return s;
     }
     record(c, stats, b0, nb, false, born ? 1 : 2);
-    gradient<T>(nb, N, born ? nullptr : (const C<T>*)c->f[F_U], c->inc, (const C<T>*)c->f[F_W], scale,
-                b0 > 0 ? 1 : 0, (T*)g, c->stream);
+    gradient<T>(nb, N, born ? nullptr : field, c->inc, (const C<T>*)we, scale, b0 > 0 ? 1 : 0, (T*)g,
+                c->stream);
     if (bq_status s = check_launch(c, "grad")) return s;
     const size_t npart = (size_t)nb * c->np_det;
     HIPCHK(c, hipMemcpyAsync(c->hpart, c->part_det, npart * sizeof(double), hipMemcpyDeviceToHost,
@@ -567,6 +592,14 @@ bq_status bq_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   if (!c) return BQ_EINVAL;
   return c->g.precision == BQ_F32 ? do_grad<float>(c, x, y, idx, B, scale, g_out, loss, st)
                                   : do_grad<double>(c, x, y, idx, B, scale, g_out, loss, st);
+}
+
+bq_status bq_grad_ws(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, void* g_out,
+                     double* loss, bq_solve_stats* st, void* u_io, void* w_io, int start) {
+  if (!c) return BQ_EINVAL;
+  if (!u_io || !w_io) return set_err(c, BQ_EINVAL, "u_io and w_io are required");
+  return c->g.precision == BQ_F32 ? do_grad<float>(c, x, y, idx, B, scale, g_out, loss, st, u_io, w_io, start)
+                                  : do_grad<double>(c, x, y, idx, B, scale, g_out, loss, st, u_io, w_io, start);
 }
 
 bq_status bq_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B, double scale, double* loss,

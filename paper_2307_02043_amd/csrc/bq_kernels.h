@@ -105,6 +105,7 @@ template <typename T> void vec_s(const VecArgs<T>& a, hipStream_t st);
 template <typename T> void vec_xr(const VecArgs<T>& a, hipStream_t st);
 template <typename T> void vec_norm(const VecArgs<T>& a, const C<T>* f, hipStream_t st);
 template <typename T> void vec_fill_incident(int B, int N, const C<double>* inc, C<T>* out, hipStream_t st);
+template <typename T> void vec_zero_if_b0(int B, size_t V, const SysState* st, C<T>* e, hipStream_t s);
 
 void sc_init(int B, SysState* st, const double* part_r, int np_r, const double* part_b, int np_b,
              double bnorm2_fixed, double tol, int max_iter, hipStream_t s);

@@ -12,7 +12,10 @@
 //   k >  S: Btilde = tau* I + U U^T, tau* = sum_s tau_s, U = [u_1 .. u_S]
 //           v = x_{k-1} - a S Btilde^-1 g (Woodbury, S x S solve on the host)
 //           x_k = WPM(v; Btilde, a S lambda)
-// State per subset: xbar_s, gbar_s, u_s (3S images) and tau_s.
+// State per subset: xbar_s, gbar_s, u_s (3S images) and tau_s; with warm
+// starts also the forward and adjoint fields of the subset's illuminations,
+// from which its next solves start (bq_grad_ws).  The first-order variant
+// takes the k <= S step at every iteration.
 #include <cmath>
 #include <string>
 #include <vector>
@@ -142,6 +145,8 @@ struct bq_qn {
   void* g = nullptr;
   void* v = nullptr;
   void* ybuf = nullptr;
+  void* ufields = nullptr;  // warm start: per subset, its illuminations' forward fields
+  void* wfields = nullptr;  // and conjugated adjoint fields
   double* part = nullptr;
   double* res = nullptr;
   double* hres = nullptr;  // pinned
@@ -156,7 +161,7 @@ thread_local std::string g_qn_create_error;
 
 void free_qn(bq_qn* q) {
   if (!q) return;
-  void* ptrs[] = {q->xbar, q->gbar, q->U, q->g, q->v, q->ybuf, q->part, q->res};
+  void* ptrs[] = {q->xbar, q->gbar, q->U, q->g, q->v, q->ybuf, q->ufields, q->wfields, q->part, q->res};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (q->hres) (void)hipHostFree(q->hres);
@@ -276,10 +281,16 @@ bq_status qn_step(bq_qn* q, void* xv, const void* y, int pick, bq_qn_info* info)
       return qn_fail(q, BQ_EDEVICE, "gather of the subset measurements failed");
   if (hipStreamSynchronize(q->stream) != hipSuccess) return qn_fail(q, BQ_EDEVICE, "device error");
   double loss = 0.0;
-  const bq_status sg = bq_grad(q->ls, x, q->ybuf, &q->idx[q->off[sp]], q->len[sp], (double)S / q->L, g, &loss,
-                               nullptr);
+  bq_status sg;
+  if (p.warm_start) {
+    const size_t fo = (size_t)q->off[sp] * V * q->csz;
+    sg = bq_grad_ws(q->ls, x, q->ybuf, &q->idx[q->off[sp]], q->len[sp], (double)S / q->L, g, &loss, nullptr,
+                    (char*)q->ufields + fo, (char*)q->wfields + fo, q->seen[sp]);
+  } else {
+    sg = bq_grad(q->ls, x, q->ybuf, &q->idx[q->off[sp]], q->len[sp], (double)S / q->L, g, &loss, nullptr);
+  }
   if (sg < 0) return qn_fail(q, sg, std::string("gradient: ") + bq_last_error(q->ls));
-  if (q->seen[sp])
+  if (q->seen[sp] && !p.first_order)
     if (bq_status s = qn_sr1<T>(q, sp, x, g)) return s;
   if (hipMemcpyAsync((T*)q->xbar + (size_t)sp * V, x, V * sizeof(T), hipMemcpyDeviceToDevice, q->stream) !=
           hipSuccess ||
@@ -291,7 +302,7 @@ bq_status qn_step(bq_qn* q, void* xv, const void* y, int pick, bq_qn_info* info)
   bq_status sx;
   double tau_sum;
   int rank;
-  if (k <= S) {
+  if (k <= S || p.first_order) {
     tau_sum = p.alpha;
     rank = 0;
     QnCoef w{};
@@ -368,6 +379,10 @@ bq_status bq_qn_create(bq_ctx* ls, bq_prox* px, const bq_qn_params* prm, const i
     g_qn_create_error = "tv or cset";
     return BQ_EINVAL;
   }
+  if (p.warm_start && ls->g.model != BQ_MODEL_LS) {
+    g_qn_create_error = "warm starts need the LS model";
+    return BQ_EUNSUPPORTED;
+  }
   const int N = ls->g.N;
   if (px->prec != ls->g.precision || px->nz != N || px->ny != N || px->nx != N) {
     g_qn_create_error = "the prox workspace must have the context's precision and an N x N x N image";
@@ -410,7 +425,9 @@ bq_status bq_qn_create(bq_ctx* ls, bq_prox* px, const bq_qn_params* prm, const i
       hipMalloc(&q->ybuf, (size_t)q->maxlen * N * N * q->csz) != hipSuccess ||
       hipMalloc((void**)&q->part, (size_t)q->np * QN_K * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&q->res, QN_K * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&q->hres, QN_K * sizeof(double)) != hipSuccess) {
+      hipHostMalloc((void**)&q->hres, QN_K * sizeof(double)) != hipSuccess ||
+      (p.warm_start && (hipMalloc(&q->ufields, (size_t)total * q->V * q->csz) != hipSuccess ||
+                        hipMalloc(&q->wfields, (size_t)total * q->V * q->csz) != hipSuccess))) {
     free_qn(q);
     g_qn_create_error = "out of memory";
     return BQ_ENOMEM;

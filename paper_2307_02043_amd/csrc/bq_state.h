@@ -58,6 +58,8 @@ enum ZiMode : int {
   ZI_AV_RHAT = 2,   // out = v - G w ; partial <rhat, out>
   ZI_AS_TS = 3,     // out = s - G w ; partials <out, s>, <out, out>
   ZI_G_NORM = 4,    // out = out2 = G w ; partial ||out||^2
+  ZI_RES_NORM = 5,  // out = out2 = b - e0 + G w (e0 in vz; b = bsrc, or the
+                    // plane wave from inc when bsrc is null) ; partial ||out||^2
 };
 
 template <typename T>
@@ -79,7 +81,8 @@ struct PassArgs {
   const C<T>* twH;             // exp(-i pi n / N), n < N
   // z-inverse epilogue
   int zi_mode;
-  const C<T>* vz;              // v (ZI_AV_RHAT) or s (ZI_AS_TS)
+  const C<T>* vz;              // v (ZI_AV_RHAT), s (ZI_AS_TS) or e0 (ZI_RES_NORM)
+  const C<T>* bsrc;            // right-hand side b (ZI_RES_NORM), null: plane wave
   const C<T>* rhat;
   C<T>* out;
   C<T>* out2;

@@ -374,6 +374,31 @@ __global__ void __launch_bounds__(NT) k_zi(PassArgs<T> a) {
           red[2] += (double)o.x * o.x + (double)o.y * o.y;
         }
     } break;
+    case ZI_RES_NORM: {  // r0 = b - e0 + G w for a solve started from e0
+      C<T> o[EPT];
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          const size_t n = nof(s);
+          C<T> bv;
+          if (a.bsrc) {
+            bv = a.bsrc[n];
+          } else {
+            const int e = tid + s * NT, z = e / TX, x = x0 + (e - z * TX);
+            const C<double>* t = a.inc + (size_t)b * 3 * N;
+            bv = cvt<T>(cmul(cmul(t[x], t[N + y]), t[2 * N + z]));
+          }
+          o[s] = bv - a.vz[n];
+        }
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          o[s] = o[s] + acc[s];
+          a.out[nof(s)] = o[s];
+          a.out2[nof(s)] = o[s];
+          red[2] += (double)o[s].x * o[s].x + (double)o[s].y * o[s].y;
+        }
+    } break;
     default:  // ZI_G_NORM
 #pragma unroll
       for (int s = 0; s < EPT; ++s)

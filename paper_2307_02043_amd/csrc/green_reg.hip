@@ -126,6 +126,30 @@ __device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, 
         red[2] += (double)o.x * o.x + (double)o.y * o.y;
       }
     } break;
+    case ZI_RES_NORM: {  // r0 = b - e0 + G w for a solve started from e0
+      const C<T>* e0 = a.vz + (size_t)b * V + L;
+      C<T> o[H];
+      if (a.bsrc) {
+        const C<T>* bs = a.bsrc + (size_t)b * V + L;
+#pragma unroll
+        for (int m = 0; m < H; ++m) o[m] = bs[(size_t)(j + R2 * m) * N2] - e0[(size_t)(j + R2 * m) * N2];
+      } else {
+        const int y = L / N, x = L - y * N;
+        const C<double>* t = a.inc + (size_t)b * 3 * N;
+        const C<double> txy = cmul(t[x], t[N + y]);
+#pragma unroll
+        for (int m = 0; m < H; ++m)
+          o[m] = cvt_r<T>(cmul(txy, t[2 * N + j + R2 * m])) - e0[(size_t)(j + R2 * m) * N2];
+      }
+      C<T>* out2 = a.out2 + (size_t)b * V + L;
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        o[m] = o[m] + gw[m];
+        out[(size_t)(j + R2 * m) * N2] = o[m];
+        out2[(size_t)(j + R2 * m) * N2] = o[m];
+        red[2] += (double)o[m].x * o[m].x + (double)o[m].y * o[m].y;
+      }
+    } break;
     default: {  // ZI_G_NORM
       C<T>* out2 = a.out2 ? a.out2 + (size_t)b * V + L : nullptr;
 #pragma unroll

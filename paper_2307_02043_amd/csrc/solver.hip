@@ -126,6 +126,21 @@ __global__ void __launch_bounds__(VEC_WG) k_fill_incident(int N, const C<double>
   }
 }
 
+// e_b = 0 for the systems whose right-hand side is zero (their solution),
+// after a solve started from a given point
+template <typename T>
+__global__ void __launch_bounds__(VEC_WG) k_zero_if_b0(const SysState* st, C<T>* e, size_t V) {
+  const int b = blockIdx.z;
+  if (st[b].bnorm2 != 0.0) return;
+  for (size_t i = blockIdx.x * (size_t)VEC_WG + threadIdx.x; i < V; i += (size_t)gridDim.x * VEC_WG)
+    e[(size_t)b * V + i] = C<T>{0, 0};
+}
+
+template <typename T>
+void vec_zero_if_b0(int B, size_t V, const SysState* st, C<T>* e, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero_if_b0<T>), dim3(vec_num_partials(V), 1, B), dim3(VEC_WG), 0, s, st, e, V);
+}
+
 template <typename T>
 void vec_p(const VecArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_vec_p<T>), dim3(vec_num_partials(a.V), 1, a.B), dim3(VEC_WG), 0, st, a);
@@ -428,6 +443,7 @@ void gradient(int B, int N, const C<T>* u, const C<double>* inc, const C<T>* wba
   template void vec_xr<T>(const VecArgs<T>&, hipStream_t);                                          \
   template void vec_norm<T>(const VecArgs<T>&, const C<T>*, hipStream_t);                           \
   template void vec_fill_incident<T>(int, int, const C<double>*, C<T>*, hipStream_t);               \
+  template void vec_zero_if_b0<T>(int, size_t, const SysState*, C<T>*, hipStream_t);                 \
   template void detector<T>(int, int, const C<T>*, int, const C<double>*, const C<T>*, C<T>*,        \
                             double*, int, hipStream_t);                                             \
   template void gradient<T>(int, int, const C<T>*, const C<double>*, const C<T>*, double, int, T*,   \

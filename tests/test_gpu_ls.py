@@ -232,3 +232,39 @@ def test_pass_timing_mask(dev):
     assert lib.bq_timing(ctx._h, L.BQ_TIMING_ALL + 1) == L.BQ_EINVAL
     assert lib.bq_timing(ctx._h, -1) == L.BQ_EINVAL
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,plain", [("f64", False), ("f64", True), ("f32", False)])
+def test_warm_started_grad_matches_oracle(dev, prec, plain):
+    """bq_grad_ws: the fields of a gradient at x start the solves of the
+    gradient at a nearby x1; gradient, loss and fields match the oracle's
+    warm-started computation, with fewer iterations than a cold start."""
+    x, y, dirs, idx, _, _ = _c1_reference()
+    N = x.shape[0]
+    m = _model(N)
+    x1 = 1.02 * x
+    _, _, _, fields = m.grad(x, y, dirs, idx, 0.25, 1e-13, 400, return_fields=True)
+    gref, fref, stref, fref1 = m.grad(x1, y, dirs, idx, 0.25, 1e-13, 400, starts=fields, return_fields=True)
+    rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    tol = 1e-13 if prec == "f64" else 1e-6
+    ctx = _ctx(N, dirs, prec, tol=tol, max_iter=400, plain=plain)
+    B = len(idx)
+    u = torch.zeros((B, N, N, N), dtype=cd, device=dev)
+    w = torch.zeros_like(u)
+    yt = torch.from_numpy(y).to(dev, cd)
+    ctx.grad_ws(torch.from_numpy(x).to(dev, rd), yt, idx, 0.25, u, w, start=False)
+    gc, fc, ic = ctx.grad(torch.from_numpy(x1).to(dev, rd), yt, idx, 0.25)
+    g, f, info = ctx.grad_ws(torch.from_numpy(x1).to(dev, rd), yt, idx, 0.25, u, w, start=True)
+    assert info.status == 0
+    lim = 1e-10 if prec == "f64" else 2e-4
+    assert _rel(g.cpu().numpy(), gref) < lim
+    assert abs(f - fref) / fref < lim
+    for b in range(B):
+        assert _rel(u[b].cpu().numpy(), fref1[b][0]) < lim
+        # the library keeps the conjugated adjoint field (it solves the conjugate system)
+        assert _rel(w[b].cpu().numpy(), np.conj(fref1[b][1])) < lim
+    assert sum(info.iters_fwd) + sum(info.iters_adj) < sum(ic.iters_fwd) + sum(ic.iters_adj)
+    if prec == "f64":
+        assert list(info.iters_fwd) == [s[0] for s in stref]
+        assert list(info.iters_adj) == [s[1] for s in stref]
+    ctx.close()

@@ -58,12 +58,17 @@ def _params(tau_max):
 
 
 @functools.lru_cache(maxsize=None)
-def _oracle_run(tau_max, draws):
+def _oracle_run(tau_max, draws, warm=False, first_order=False):
     xt, dirs, m, y = _problem()
-    prm = bqnpm.BQNPMParams(**_params(tau_max))
+    prm = bqnpm.BQNPMParams(**_params(tau_max), first_order=first_order)
+    store = {}
 
     def grad(s, x):
-        return m.grad(x, y[SUBSETS[s]], dirs, SUBSETS[s], S / L, 1e-13, 400)[0]
+        starts = store.get(s) if warm else None
+        g, _, _, fields = m.grad(x, y[SUBSETS[s]], dirs, SUBSETS[s], S / L, 1e-13, 400, starts=starts,
+                                 return_fields=True)
+        store[s] = fields
+        return g
     it = bqnpm.BQNPM(prm, grad)
     x = np.zeros_like(xt)
     out = []
@@ -73,7 +78,7 @@ def _oracle_run(tau_max, draws):
     return out
 
 
-def _gpu_run(dev, prec, tau_max, draws):
+def _gpu_run(dev, prec, tau_max, draws, warm=False, first_order=False):
     from paper_2307_02043_amd import LSContext, QNIteration, WProx
     xt, dirs, m, y = _problem()
     p = _params(tau_max)
@@ -82,7 +87,7 @@ def _gpu_run(dev, prec, tau_max, draws):
     ls = LSContext(N, H, syn.LAMBDA0_UM, syn.N_B, dirs, precision=prec, tol=tol, max_iter=400)
     px = WProx((N, N, N), prec)
     qn = QNIteration(ls, px, SUBSETS, p["a"], p["lam"], p["alpha"], p["gamma"], p["tau_max"],
-                     prox_iters=p["prox_iters"])
+                     prox_iters=p["prox_iters"], warm_start=warm, first_order=first_order)
     x = torch.zeros((N, N, N), dtype=rd, device=dev)
     yt = torch.from_numpy(y).to(dev, cd)
     out = []
@@ -150,3 +155,17 @@ def test_qn_rejects_bad_arguments(dev):
     px.close()
     px32.close()
     ls.close()
+
+
+@pytest.mark.parametrize("warm,first_order", [(True, False), (False, True), (True, True)])
+def test_qn_variants_f64_match_oracle(dev, warm, first_order):
+    """Warm-started solves across outer iterations and the first-order
+    (alpha I) variant of the outer loop, against the oracle."""
+    ref = _oracle_run(5e-5, STRAT_I, warm, first_order)
+    got = _gpu_run(dev, "f64", 5e-5, STRAT_I, warm, first_order)
+    for k, ((xr, sp, tau, uk), (xg, info)) in enumerate(zip(ref, got), start=1):
+        assert info.subset == sp
+        if first_order:
+            assert info.metric_rank == 0 and info.tau_sum == _params(5e-5)["alpha"]
+        err = _rel(xg, xr)
+        assert err < 1e-9, (k, err)

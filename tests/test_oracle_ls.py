@@ -6,7 +6,10 @@
 * at x = 0 the LS gradient is exactly the first-Born gradient;
 * adjoint identity <J v, w> = <v, J^H w>, with J v from an independent
   tangent solve;
-* the gradient matches FP64 central finite differences of the loss on 16^3.
+* the gradient matches FP64 central finite differences of the loss on 16^3;
+* warm-started solves (a given starting point) reach the dense solutions,
+  return the start unchanged when it is exact and zero for a zero
+  right-hand side; the warm-started gradient equals the cold one.
 """
 import math
 
@@ -151,3 +154,60 @@ def test_gradient_matches_central_differences():
         checks.append((fd, float(g.ravel()[flat])))
     for fd, an in checks:
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.max(np.abs(g))), (fd, an)
+
+
+def test_warm_started_solves():
+    """Warm start: from the exact solution no iteration is taken and the
+    start is returned; from a perturbed start the solve reaches the dense
+    solution of the forward and adjoint systems; a zero right-hand side
+    gives zero whatever the start."""
+    N = 8
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    x = _phantom(N, 7) + 3.0
+    d = syn.illumination_directions(1, 35.0, np.random.default_rng(3))[0]
+    uin = lsmodel.incident_field(geom, d)
+    A = _dense_operator(model, x)
+    ud = np.linalg.solve(A, uin.ravel()).reshape(uin.shape)
+    u, it, st, _ = model.solve_forward(x, uin, 1e-12, 500, e0=ud)
+    assert it == 0 and st == lsmodel.CONVERGED and np.array_equal(u, ud)
+    rng = np.random.default_rng(4)
+    start = ud + 0.05 * (rng.standard_normal(ud.shape) + 1j * rng.standard_normal(ud.shape))
+    u, it, st, _ = model.solve_forward(x, uin, 1e-14, 500, e0=start)
+    assert st == lsmodel.CONVERGED and it > 0
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-12
+    # adjoint system (I - G^H X) w = z from a random start, vs the dense solve
+    z = rng.standard_normal(ud.shape) + 1j * rng.standard_normal(ud.shape)
+    AH = np.empty_like(A)
+    e = np.zeros(N ** 3, dtype=np.complex128)
+    for j in range(N ** 3):
+        e[:] = 0
+        e[j] = 1
+        col = e.reshape(N, N, N)
+        AH[:, j] = (col - model.GH(x * col)).ravel()
+    wd = np.linalg.solve(AH, z.ravel()).reshape(z.shape)
+    w, it, st, _ = model.solve_adjoint(x, z, 1e-14, 500, e0=start)
+    assert st == lsmodel.CONVERGED
+    assert np.linalg.norm(w - wd) / np.linalg.norm(wd) < 1e-12
+    w0, it0, st0, _ = model.solve_adjoint(x, np.zeros_like(z), 1e-14, 500, e0=start)
+    assert it0 == 0 and st0 == lsmodel.CONVERGED and not np.any(w0)
+
+
+def test_warm_started_gradient_equals_cold_gradient():
+    """The gradient does not depend on where the solves start (to the solve
+    tolerance), and a start near the solution saves iterations."""
+    N = 12
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    xt = _phantom(N, 11)
+    dirs = syn.illumination_directions(3, 35.0, np.random.default_rng(12))
+    idx = [0, 2]
+    y, _ = model.forward(xt, dirs, idx, 1e-13, 400)
+    x = 0.5 * xt
+    g0, f0, st0, fields = model.grad(x, y, dirs, idx, 0.5, 1e-13, 400, return_fields=True)
+    x1 = x * 1.02
+    gc, fc, stc = model.grad(x1, y, dirs, idx, 0.5, 1e-13, 400)
+    gw, fw, stw = model.grad(x1, y, dirs, idx, 0.5, 1e-13, 400, starts=fields)
+    assert np.linalg.norm(gw - gc) / np.linalg.norm(gc) < 1e-10
+    assert abs(fw - fc) < 1e-10 * fc
+    assert sum(s[0] + s[1] for s in stw) < sum(s[0] + s[1] for s in stc)
