@@ -12,6 +12,12 @@ model to its supplement):
 
 * field equation (I - G diag(x)) u_l = u_in,l with u_in,l = exp(j k_l . r);
 * H_l(x) = S (u_l - u_in,l), S = the z = N-1 plane (N x N detector);
+  optionally the detector is a plane at distance d beyond it: the
+  scattered field on the exit plane, taken as periodic over the N x N
+  lateral window, is propagated by the angular spectrum
+  P_d = F^-1 diag(exp(j k_z d)) F, k_z = sqrt(kb^2 - kx^2 - ky^2) for
+  propagating and j sqrt(kx^2 + ky^2 - kb^2) for evanescent components
+  (the paper's off-grid cameras need a geometry it does not give);
 * BiCGSTAB started at the right-hand side, shadow residual r^ = r_0,
   relative recursive-residual stopping test, early exit on ||s||;
 * gradient of f_l = Re(conj(u_l) . w_l) where w_l solves
@@ -39,6 +45,7 @@ class Geometry:
     h: float          # voxel edge (um)
     lambda0: float    # vacuum wavelength (um)
     n_b: float        # background refractive index
+    det_dist: float = 0.0  # detector distance beyond the exit plane (um); 0: the exit plane
 
     @property
     def k0(self) -> float:
@@ -52,6 +59,23 @@ class Geometry:
 def voxel_axis(N: int, h: float) -> np.ndarray:
     """Voxel centres (i - (N-1)/2) h along one axis."""
     return (np.arange(N) - (N - 1) / 2.0) * h
+
+
+def transfer_function(geom: Geometry, d: float) -> np.ndarray:
+    """Angular-spectrum transfer function exp(j k_z d) on the N x N lateral
+    frequency grid (FFT order, [ky][kx]), k_z = sqrt(kb^2 - |k_perp|^2) with
+    the root j sqrt(|k_perp|^2 - kb^2) for evanescent components."""
+    k = 2.0 * math.pi * np.fft.fftfreq(geom.N, d=geom.h)
+    kp2 = k[:, None] ** 2 + k[None, :] ** 2
+    kz2 = geom.kb ** 2 - kp2
+    kz = np.where(kz2 >= 0, np.sqrt(np.maximum(kz2, 0.0)) + 0j, 1j * np.sqrt(np.maximum(-kz2, 0.0)))
+    return np.exp(1j * kz * d)
+
+
+def propagate(plane: np.ndarray, geom: Geometry, d: float, adjoint: bool = False) -> np.ndarray:
+    """P_d (or its adjoint) applied to an (N, N) field [y][x]."""
+    T = transfer_function(geom, d)
+    return np.fft.ifft2((np.conj(T) if adjoint else T) * np.fft.fft2(plane))
 
 
 def incident_field(geom: Geometry, direction) -> np.ndarray:
@@ -127,12 +151,18 @@ class LSModel:
         return green.apply_GH(self.ghat, v, workers=self.workers)
 
     def detector(self, field):
-        """S: the z = N-1 plane of a field, shape (N, N)."""
+        """S: the z = N-1 plane of a field, shape (N, N), propagated to the
+        detector plane when det_dist > 0."""
+        if self.geom.det_dist > 0:
+            return propagate(field[-1], self.geom, self.geom.det_dist)
         return field[-1]
 
     def detector_T(self, r):
-        """S^T: embed an (N, N) detector image into the z = N-1 plane."""
+        """S^T (the adjoint of detector): embed an (N, N) detector image
+        (propagated back by P_d^H when det_dist > 0) into the z = N-1 plane."""
         N = self.geom.N
+        if self.geom.det_dist > 0:
+            r = propagate(r, self.geom, self.geom.det_dist, adjoint=True)
         out = np.zeros((N, N, N), dtype=np.complex128)
         out[-1] = r
         return out
