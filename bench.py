@@ -334,6 +334,10 @@ def main():
                           f"3 extra applications of G")}
         log(f"oracle: {t_iter:.2f} s per BiCGSTAB iteration")
 
+    # ---- propagated detector plane (angular spectrum), same workload ---------
+    det = bench_detprop(w, dev, xt, dirs, idx, scale, args.steps, 1e3 * elapsed / args.steps) \
+        if args.steps > 0 else None
+
     # ---- outer iteration of the method on the same workload -----------------
     qn = None
     if args.qn_iters > 0:
@@ -372,8 +376,37 @@ def main():
         "passes_ms_per_step": {k: round(v / breakdown_steps, 3) for k, v in warm_ms.items()},
         "prox": prox,
         "qn": qn,
+        "detector_propagation": det,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_detprop(w, dev, xt, dirs, idx, scale, steps, base_ms, d_um=1.0):
+    """The batched FP32 gradient of the workload with the detector plane
+    d_um beyond the exit plane (angular-spectrum propagation before the
+    residual and its adjoint before the adjoint right-hand side)."""
+    import torch
+
+    from paper_2307_02043_amd import LSContext
+
+    ctx = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=1e-6, max_iter=w.max_iter,
+                    det_dist_um=d_um)
+    xtt = torch.from_numpy(xt).to(dev, torch.float32)
+    y = ctx.forward(xtt, idx)[0]
+    ctx.close()
+    ctx = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol, max_iter=w.max_iter,
+                    det_dist_um=d_um)
+    x = (0.5 * xtt).contiguous()
+    ctx.grad(x, y, idx, scale)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.grad(x, y, idx, scale)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / steps * 1e3
+    ctx.close()
+    log(f"detector plane {d_um} um beyond the exit plane: {ms:.2f} ms per gradient step")
+    return {"det_dist_um": d_um, "ms_per_step": round(ms, 3), "exit_plane_ms_per_step": round(base_ms, 3)}
 
 
 def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):

@@ -78,6 +78,12 @@ typedef struct {
   double tol;        /* BiCGSTAB relative residual tolerance (>= 0)         */
   int max_iter;      /* BiCGSTAB iteration cap (>= 0)                       */
   unsigned flags;    /* BQ_FLAG_*                                           */
+  double det_dist_um; /* detector plane distance beyond the exit plane z =
+                         N-1 (um, >= 0).  0: the detector is the exit plane.
+                         > 0: the exit-plane scattered field, periodic over
+                         the N x N window, is propagated by the angular
+                         spectrum exp(i k_z d) (evanescent parts decaying);
+                         the adjoint uses the conjugate transfer function  */
 } bq_geom;
 
 /* Unit propagation direction of a plane-wave illumination

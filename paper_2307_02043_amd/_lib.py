@@ -32,7 +32,8 @@ EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields
 class Geom(ct.Structure):
     _fields_ = [("N", ct.c_int), ("h_um", ct.c_double), ("lambda0_um", ct.c_double),
                 ("n_b", ct.c_double), ("precision", ct.c_int), ("model", ct.c_int),
-                ("tol", ct.c_double), ("max_iter", ct.c_int), ("flags", ct.c_uint)]
+                ("tol", ct.c_double), ("max_iter", ct.c_int), ("flags", ct.c_uint),
+                ("det_dist_um", ct.c_double)]
 
 
 class Illum(ct.Structure):

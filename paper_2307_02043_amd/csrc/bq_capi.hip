@@ -1,5 +1,6 @@
 // C ABI of the bq library: contexts, argument checking, and the host-side
 // driver of the batched and per-illumination ("plain") solve paths.
+#include <cmath>
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
@@ -148,6 +149,28 @@ bq_status check_launch(bq_ctx* c, const char* where) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, where);
   return BQ_OK;
+}
+
+// Detector images of nb systems: out = P S(field - sub u_in), and with y
+// given r = out - y with the loss partials; P = identity, or the angular-
+// spectrum propagation to the detector plane when det_dist_um > 0.
+template <typename T>
+void det_images(bq_ctx* c, int nb, const C<T>* field, int sub, const C<T>* y, C<T>* out, double* part) {
+  const int N = c->g.N;
+  if (!c->dettab) {
+    detector<T>(nb, N, field, sub, c->inc, y, out, part, c->np_det, c->stream);
+    return;
+  }
+  detector<T>(nb, N, field, sub, c->inc, nullptr, out, nullptr, c->np_det, c->stream);
+  plane_propagate<T>(nb, N, out, (const C<T>*)c->twN, (const C<T>*)c->dettab, 0, c->stream);
+  if (y) det_residual<T>(nb, N, out, y, part, c->np_det, c->stream);
+}
+
+// P^H applied to the residual images before the adjoint right-hand side
+template <typename T>
+void det_adjoint(bq_ctx* c, int nb) {
+  if (c->dettab)
+    plane_propagate<T>(nb, c->g.N, (C<T>*)c->rdet, (const C<T>*)c->twN, (const C<T>*)c->dettab, 1, c->stream);
 }
 
 // BiCGSTAB for B systems (I - G diag(x)) e_b = b_b.
@@ -328,15 +351,13 @@ bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out,
       a.zi_mode = ZI_G;
       a.out = (C<T>*)c->f[F_V];
       if (green_apply<T>(a, c->stream, &c->timer)) return set_err(c, BQ_EUNSUPPORTED, "grid size");
-      detector<T>(nb, N, (const C<T>*)c->f[F_V], 0, c->inc, nullptr, (C<T>*)out + (size_t)b0 * N2,
-                  nullptr, c->np_det, c->stream);
+      det_images<T>(c, nb, (const C<T>*)c->f[F_V], 0, nullptr, (C<T>*)out + (size_t)b0 * N2, nullptr);
       for (int b = 0; b < nb; ++b) { c->hstate[b] = SysState{}; c->hstate[b].status = SYS_CONVERGED; }
       extra = 1;
     } else {
       if (bq_status s = forward_fields<T>(c, (const T*)x, nb, u, plain)) return s;
       if (!want_fields)
-        detector<T>(nb, N, (const C<T>*)u, 1, c->inc, nullptr, (C<T>*)out + (size_t)b0 * N2, nullptr,
-                    c->np_det, c->stream);
+        det_images<T>(c, nb, (const C<T>*)u, 1, nullptr, (C<T>*)out + (size_t)b0 * N2, nullptr);
     }
     if (bq_status s = check_launch(c, "forward")) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -383,8 +404,7 @@ bq_status do_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B
       sub = 1;
     }
     record(c, stats, b0, nb, true, 1);
-    detector<T>(nb, N, field, sub, c->inc, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det,
-                c->np_det, c->stream);
+    det_images<T>(c, nb, field, sub, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det);
     if (bq_status s = check_launch(c, "loss")) return s;
     const size_t npart = (size_t)nb * c->np_det;
     HIPCHK(c, hipMemcpyAsync(c->hpart, c->part_det, npart * sizeof(double), hipMemcpyDeviceToHost,
@@ -441,9 +461,9 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
       sub = 1;
     }
     record(c, stats, b0, nb, true, 1);
-    detector<T>(nb, N, field, sub, c->inc, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det,
-                c->np_det, c->stream);
-    // adjoint right-hand side (conjugated): G S^T conj(r); for a warm start
+    det_images<T>(c, nb, field, sub, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det);
+    det_adjoint<T>(c, nb);
+    // adjoint right-hand side (conjugated): G S^T conj(P^H r); for a warm start
     // it goes to the p buffer (free until the first iteration) and the solve
     // starts from w_io
     const bool warm_adj = ws && start;
@@ -510,6 +530,31 @@ bq_status create_tables(bq_ctx* c) {
   HIPCHK(c, hipMalloc(&c->twH, N * sizeof(C<T>)));
   HIPCHK(c, hipMemcpy(c->twN, tn.data(), N * sizeof(C<T>), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->twH, th.data(), N * sizeof(C<T>), hipMemcpyHostToDevice));
+  if (c->g.det_dist_um > 0) {
+    // exp(i k_z d) / N^2 on the lateral frequency grid (FFT order [ky][kx])
+    std::vector<C<T>> tf((size_t)N * N);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double kb = (long double)c->kb, d = (long double)c->g.det_dist_um;
+    const long double dk = 2.0L * pi / ((long double)N * (long double)c->g.h_um);
+    for (int iy = 0; iy < N; ++iy)
+      for (int ix = 0; ix < N; ++ix) {
+        const long double ky = dk * (iy < N / 2 ? iy : iy - N), kx = dk * (ix < N / 2 ? ix : ix - N);
+        const long double kz2 = kb * kb - kx * kx - ky * ky;
+        long double re, im;
+        if (kz2 >= 0) {
+          const long double ph = sqrtl(kz2) * d;
+          re = cosl(ph);
+          im = sinl(ph);
+        } else {
+          re = expl(-sqrtl(-kz2) * d);
+          im = 0;
+        }
+        const long double sc = 1.0L / ((long double)N * (long double)N);
+        tf[(size_t)iy * N + ix] = C<T>{(T)(re * sc), (T)(im * sc)};
+      }
+    HIPCHK(c, hipMalloc(&c->dettab, (size_t)N * N * sizeof(C<T>)));
+    HIPCHK(c, hipMemcpy(c->dettab, tf.data(), (size_t)N * N * sizeof(C<T>), hipMemcpyHostToDevice));
+  }
   if (hipMalloc(&c->ghat, 8 * c->V * sizeof(C<T>)) != hipSuccess)
     return set_err(c, BQ_ENOMEM, "out of device memory (transfer function)");
   const int rc = ghat_precompute<T>(N, c->g.h_um, c->kb, (C<T>*)c->ghat, c->stream);
@@ -526,6 +571,7 @@ void destroy_ctx(bq_ctx* c) {
   if (c->ghat) (void)hipFree(c->ghat);
   if (c->twN) (void)hipFree(c->twN);
   if (c->twH) (void)hipFree(c->twH);
+  if (c->dettab) (void)hipFree(c->dettab);
   delete c;
 }
 
@@ -540,6 +586,8 @@ bq_status bq_create(const bq_geom* g, const bq_illum* dirs, int L, void* stream,
   if (!supported_N(g->N)) return set_err(nullptr, BQ_EUNSUPPORTED, "unsupported grid size N");
   if (!(g->h_um > 0) || !(g->lambda0_um > 0) || !(g->n_b > 0) || !(g->tol >= 0) || g->max_iter < 0)
     return set_err(nullptr, BQ_EINVAL, "h, lambda0, n_b must be > 0; tol, max_iter >= 0");
+  if (!(g->det_dist_um >= 0) || !std::isfinite(g->det_dist_um))
+    return set_err(nullptr, BQ_EINVAL, "det_dist_um must be finite and >= 0");
   if (g->precision != BQ_F32 && g->precision != BQ_F64) return set_err(nullptr, BQ_EINVAL, "precision");
   if (g->model != BQ_MODEL_LS && g->model != BQ_MODEL_BORN) return set_err(nullptr, BQ_EINVAL, "model");
   for (int l = 0; l < L; ++l) {

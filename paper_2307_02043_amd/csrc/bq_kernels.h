@@ -79,6 +79,8 @@ template <typename T> int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTi
 int reg_num_partials(int N);
 template <typename T> int xy_fused_launch(const PassArgs<T>& a, hipStream_t st);
 template <typename T> int ghat_precompute(int N, double h, double kb, C<T>* out, hipStream_t st);
+template <typename T>
+int plane_propagate(int B, int N, C<T>* planes, const C<T>* twN, const C<T>* tf, int adjoint, hipStream_t st);
 int ghat_oversampling(int N);
 
 // ---- BiCGSTAB and the data term -------------------------------------------
@@ -106,6 +108,8 @@ template <typename T> void vec_xr(const VecArgs<T>& a, hipStream_t st);
 template <typename T> void vec_norm(const VecArgs<T>& a, const C<T>* f, hipStream_t st);
 template <typename T> void vec_fill_incident(int B, int N, const C<double>* inc, C<T>* out, hipStream_t st);
 template <typename T> void vec_zero_if_b0(int B, size_t V, const SysState* st, C<T>* e, hipStream_t s);
+template <typename T>
+void det_residual(int B, int N, C<T>* rdet, const C<T>* ymeas, double* partial, int np, hipStream_t st);
 
 void sc_init(int B, SysState* st, const double* part_r, int np_r, const double* part_b, int np_b,
              double bnorm2_fixed, double tol, int max_iter, hipStream_t s);

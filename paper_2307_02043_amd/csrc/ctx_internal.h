@@ -24,6 +24,7 @@ struct bq_ctx {
   void* ghat = nullptr;
   void* twN = nullptr;
   void* twH = nullptr;
+  void* dettab = nullptr;  // detector transfer function / N^2 (N x N, [ky][kx]) when det_dist_um > 0
   void* f[8] = {};  // u w r rhat p v s t
   void* zh = nullptr;
   void* xh = nullptr;

@@ -486,6 +486,102 @@ BQ_XI(float, 16) BQ_XI(float, 32) BQ_XI(float, 64) BQ_XI(float, 128) BQ_XI(float
 BQ_XI(double, 16) BQ_XI(double, 32) BQ_XI(double, 64) BQ_XI(double, 128) BQ_XI(double, 256)
 #undef BQ_XI
 
+// ===========================================================================
+// Propagation of B detector planes (N x N, [y][x]) by a transfer function on
+// the lateral frequency grid: out = F^-1 diag(t) F in, t in FFT order
+// [ky][kx] with the 1/N^2 of the inverse folded in (conj(t) for the
+// adjoint).  Rows forward, columns forward-multiply-inverse, rows inverse,
+// in place.
+// ===========================================================================
+template <typename T, int N, bool INV>
+__global__ void __launch_bounds__(NT) k_plane_rows(C<T>* planes, const C<T>* twN) {
+  constexpr int TL = tile_w<T>(N), LS = N + 1, TOT = TL * N, EPT = (TOT + NT - 1) / NT;
+  __shared__ C<T> lds[TL * LS];
+  __shared__ C<T> tw[N];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tw[i] = twN[i];
+  C<T>* rows = planes + (size_t)blockIdx.z * N * N + (size_t)blockIdx.x * TL * N;
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int e = tid + s * NT;
+    if ((TOT % NT) == 0 || e < TOT) {
+      const int rl = e / N, x = e - rl * N;
+      lds[rl * LS + x] = rows[e];
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N, TL, NT, INV>(lds, LS, 1, tw);
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int e = tid + s * NT;
+    if ((TOT % NT) == 0 || e < TOT) {
+      const int rl = e / N, x = e - rl * N;
+      rows[e] = lds[rl * LS + x];
+    }
+  }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(NT) k_plane_cols(C<T>* planes, const C<T>* twN, const C<T>* tf, int conj_tf) {
+  constexpr int TX = tile_w<T>(N), LS = N + 1, TOT = TX * N, EPT = (TOT + NT - 1) / NT;
+  __shared__ C<T> lds[TX * LS];
+  __shared__ C<T> tw[N];
+  const int tid = threadIdx.x, x0 = blockIdx.x * TX;
+  for (int i = tid; i < N; i += NT) tw[i] = twN[i];
+  C<T>* pl = planes + (size_t)blockIdx.z * N * N;
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int e = tid + s * NT;
+    if ((TOT % NT) == 0 || e < TOT) {
+      const int y = e / TX, xo = e - y * TX;
+      lds[xo * LS + y] = pl[(size_t)y * N + x0 + xo];
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N, TX, NT, false>(lds, LS, 1, tw);
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int e = tid + s * NT;
+    if ((TOT % NT) == 0 || e < TOT) {
+      const int ky = e / TX, xo = e - ky * TX;
+      const C<T> t = tf[(size_t)ky * N + x0 + xo];
+      lds[xo * LS + ky] = conj_tf ? cmulc(lds[xo * LS + ky], t) : cmul(lds[xo * LS + ky], t);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N, TX, NT, true>(lds, LS, 1, tw);
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int e = tid + s * NT;
+    if ((TOT % NT) == 0 || e < TOT) {
+      const int y = e / TX, xo = e - y * TX;
+      pl[(size_t)y * N + x0 + xo] = lds[xo * LS + y];
+    }
+  }
+}
+
+template <typename T, int N>
+static void plane_propagate_N(int B, C<T>* planes, const C<T>* twN, const C<T>* tf, int adjoint, hipStream_t st) {
+  constexpr int TL = tile_w<T>(N);
+  hipLaunchKernelGGL((k_plane_rows<T, N, false>), dim3(N / TL, 1, B), dim3(NT), 0, st, planes, twN);
+  hipLaunchKernelGGL((k_plane_cols<T, N>), dim3(N / TL, 1, B), dim3(NT), 0, st, planes, twN, tf, adjoint);
+  hipLaunchKernelGGL((k_plane_rows<T, N, true>), dim3(N / TL, 1, B), dim3(NT), 0, st, planes, twN);
+}
+
+template <typename T>
+int plane_propagate(int B, int N, C<T>* planes, const C<T>* twN, const C<T>* tf, int adjoint, hipStream_t st) {
+  switch (N) {
+#define BQ_CASE(n) case n: plane_propagate_N<T, n>(B, planes, twN, tf, adjoint, st); break;
+    BQ_CASE(8) BQ_CASE(12) BQ_CASE(16) BQ_CASE(24) BQ_CASE(32) BQ_CASE(48) BQ_CASE(64) BQ_CASE(96)
+    BQ_CASE(128) BQ_CASE(256)
+#undef BQ_CASE
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+template int plane_propagate<float>(int, int, C<float>*, const C<float>*, const C<float>*, int, hipStream_t);
+template int plane_propagate<double>(int, int, C<double>*, const C<double>*, const C<double>*, int, hipStream_t);
+
 template int green_apply<float>(const PassArgs<float>&, hipStream_t, PassTimer*);
 template int green_apply<double>(const PassArgs<double>&, hipStream_t, PassTimer*);
 template int green_num_partials<float>(int);

@@ -404,6 +404,27 @@ void detector(int B, int N, const C<T>* field, int sub, const C<double>* inc, co
   hipLaunchKernelGGL((k_detector<T>), dim3(np, 1, B), dim3(256), 0, st, N, field, sub, inc, ymeas, out, partial);
 }
 
+// r = H - y in place on the (propagated) detector images; partial 1/2 |r|^2
+template <typename T>
+__global__ void __launch_bounds__(256) k_det_residual(int N, C<T>* rdet, const C<T>* ymeas, double* partial) {
+  __shared__ double scratch[4];
+  const int b = blockIdx.z;
+  const size_t N2 = (size_t)N * N;
+  double acc[1] = {0.0};
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < N2; i += (size_t)gridDim.x * 256) {
+    const C<T> r = rdet[(size_t)b * N2 + i] - ymeas[(size_t)b * N2 + i];
+    rdet[(size_t)b * N2 + i] = r;
+    acc[0] += 0.5 * ((double)r.x * r.x + (double)r.y * r.y);
+  }
+  block_sum<256, 1>(acc, scratch);
+  if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = acc[0];
+}
+
+template <typename T>
+void det_residual(int B, int N, C<T>* rdet, const C<T>* ymeas, double* partial, int np, hipStream_t st) {
+  hipLaunchKernelGGL((k_det_residual<T>), dim3(np, 1, B), dim3(256), 0, st, N, rdet, ymeas, partial);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_gradient(int B, int N, const C<T>* u, const C<double>* inc,
                                                   const C<T>* wbar, double scale, int accumulate, T* g) {
@@ -444,6 +465,7 @@ void gradient(int B, int N, const C<T>* u, const C<double>* inc, const C<T>* wba
   template void vec_norm<T>(const VecArgs<T>&, const C<T>*, hipStream_t);                           \
   template void vec_fill_incident<T>(int, int, const C<double>*, C<T>*, hipStream_t);               \
   template void vec_zero_if_b0<T>(int, size_t, const SysState*, C<T>*, hipStream_t);                 \
+  template void det_residual<T>(int, int, C<T>*, const C<T>*, double*, int, hipStream_t);             \
   template void detector<T>(int, int, const C<T>*, int, const C<double>*, const C<T>*, C<T>*,        \
                             double*, int, hipStream_t);                                             \
   template void gradient<T>(int, int, const C<T>*, const C<double>*, const C<T>*, double, int, T*,   \

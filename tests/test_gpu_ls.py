@@ -268,3 +268,33 @@ def test_warm_started_grad_matches_oracle(dev, prec, plain):
         assert list(info.iters_fwd) == [s[0] for s in stref]
         assert list(info.iters_adj) == [s[1] for s in stref]
     ctx.close()
+
+
+@pytest.mark.parametrize("N,prec,model", [(24, "f64", "ls"), (32, "f64", "ls"), (32, "f32", "ls"),
+                                          (24, "f64", "born")])
+def test_propagated_detector_matches_oracle(dev, N, prec, model):
+    """Detector plane 1.3 um beyond the exit plane (angular-spectrum
+    propagation): forward images, loss and gradient vs the oracle."""
+    d = 1.3
+    geom = lsmodel.Geometry(N=N, h=H, lambda0=syn.LAMBDA0_UM, n_b=syn.N_B, det_dist=d)
+    m = lsmodel.LSModel(geom, ghat_P=_ghat(N))
+    xt, dirs = _c1_like(N, 3, 50 + N)
+    idx = [2, 0]
+    yc, _ = m.forward(xt, dirs, idx, 1e-13, 400, model=model)
+    y = syn.add_noise(yc, 30.0, np.random.default_rng(9))
+    x = 0.5 * xt
+    gref, fref, _ = m.grad(x, y, dirs, idx, 0.5, 1e-13, 400, model=model)
+    rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    tol = 1e-13 if prec == "f64" else 1e-6
+    lim = 1e-10 if prec == "f64" else 2e-4
+    ctx = _ctx(N, dirs, prec, tol=tol, max_iter=400, model=model, det_dist_um=d)
+    yg, _ = ctx.forward(torch.from_numpy(xt).to(dev, rd), idx)
+    assert _rel(yg.cpu().numpy(), yc) < lim
+    yt = torch.from_numpy(y).to(dev, cd)
+    g, f, info = ctx.grad(torch.from_numpy(x).to(dev, rd), yt, idx, 0.5)
+    assert info.status == 0
+    assert _rel(g.cpu().numpy(), gref) < lim
+    assert abs(f - fref) / fref < lim
+    fl, _ = ctx.loss(torch.from_numpy(x).to(dev, rd), yt, idx, 0.5)
+    assert abs(fl - fref) / fref < lim
+    ctx.close()
