@@ -90,21 +90,30 @@ bq_status ensure_capacity(bq_ctx* c, int B) {
   return BQ_OK;
 }
 
-// Plane-wave factors exp(i kb d_a c_i), c_i = (i - (N-1)/2) h, per system.
-bq_status upload_incident(bq_ctx* c, const int* idx, int B) {
+// Plane-wave factors exp(i kb d_a c_i), c_i = (i - (N-1)/2) h, of every
+// illumination, computed once (long-double phases) when the context is made.
+void fill_incident_table(bq_ctx* c) {
   const int N = c->g.N;
-  for (int b = 0; b < B; ++b) {
-    const bq_illum& d = c->dirs[idx[b]];
+  c->inc_tab.resize((size_t)c->L * 3 * N);
+  for (int l = 0; l < c->L; ++l) {
+    const bq_illum& d = c->dirs[l];
     const double comp[3] = {d.dx, d.dy, d.dz};
     for (int a = 0; a < 3; ++a)
       for (int i = 0; i < N; ++i) {
         const long double ci = ((long double)i - (N - 1) / 2.0L) * (long double)c->g.h_um;
         const long double ph = (long double)c->kb * (long double)comp[a] * ci;
-        c->hinc[((size_t)b * 3 + a) * N + i] = C<double>{(double)cosl(ph), (double)sinl(ph)};
+        c->inc_tab[((size_t)l * 3 + a) * N + i] = C<double>{(double)cosl(ph), (double)sinl(ph)};
       }
   }
-  HIPCHK(c, hipMemcpyAsync(c->inc, c->hinc, (size_t)B * 3 * N * sizeof(C<double>),
-                           hipMemcpyHostToDevice, c->stream));
+}
+
+// The factors of systems idx[0..B) to the device (through the pinned stage).
+bq_status upload_incident(bq_ctx* c, const int* idx, int B) {
+  const size_t row = (size_t)3 * c->g.N;
+  for (int b = 0; b < B; ++b)
+    std::memcpy(c->hinc + (size_t)b * row, c->inc_tab.data() + (size_t)idx[b] * row, row * sizeof(C<double>));
+  HIPCHK(c, hipMemcpyAsync(c->inc, c->hinc, (size_t)B * row * sizeof(C<double>), hipMemcpyHostToDevice,
+                           c->stream));
   return BQ_OK;
 }
 
@@ -602,6 +611,7 @@ bq_status bq_create(const bq_geom* g, const bq_illum* dirs, int L, void* stream,
   c->dirs.assign(dirs, dirs + L);
   c->stream = (hipStream_t)stream;
   c->kb = 2.0 * M_PI * g->n_b / g->lambda0_um;
+  fill_incident_table(c);
   c->V = (size_t)g->N * g->N * g->N;
   c->csz = g->precision == BQ_F32 ? sizeof(C<float>) : sizeof(C<double>);
   c->np_vec = vec_num_partials(c->V);

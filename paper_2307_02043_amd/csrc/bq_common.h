@@ -288,6 +288,101 @@ __device__ inline void line_ifft(C<T>* d, C<T>* line, int es, int j, const C<T>*
 }
 
 // ---------------------------------------------------------------------------
+// Table-driven variant of the register line FFT for the strided-line passes.
+// The exchange slot of value (k1, jj) is k1 P + jj with P = R2 + 1: each
+// thread's writes and reads through LDS are then one base address plus
+// compile-time offsets (no per-element address arithmetic), and the odd line
+// stride LS spreads lanes of neighbouring lines over the banks.  Twiddles
+// come from per-thread rows of a table:
+//   tf[a R1 + b] = W^{a b} (a < R2, b < R1)   (forward, row of thread j)
+//   ti[b R2 + a] = W^{a b}                    (inverse, row of k1 = b)
+// which are the same table when R1 == R2.
+// ---------------------------------------------------------------------------
+template <int R1, int R2>
+struct LineX {
+  static constexpr int P = R2 + 1;
+  static constexpr int SPAN = (R1 - 1) * P + R2;
+  static constexpr int LS = SPAN | 1;
+  static constexpr int TW = R1 == R2 ? R1 * R2 : 2 * R1 * R2;  // table entries
+};
+
+// In: d[m] = x[j + R2 m].  Out: d[i R2 + k2] = X[k1 + R1 k2], k1 = j + R2 i.
+template <typename T, int R1, int R2, bool INV>
+__device__ inline void line_fft_t(C<T>* d, C<T>* line, int j, const C<T>* tf) {
+  constexpr int NI = R1 / R2, P = LineX<R1, R2>::P;
+  dftR<T, INV, R1>(d);
+  const C<T>* w = tf + j * R1;
+#pragma unroll
+  for (int k1 = 1; k1 < R1; ++k1) d[k1] = INV ? cmulc(d[k1], w[k1]) : cmul(d[k1], w[k1]);
+  C<T>* wp = line + j;
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) wp[k1 * P] = d[k1];
+  __syncthreads();
+  const C<T>* rp = line + j * P;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int jj = 0; jj < R2; ++jj) d[i * R2 + jj] = rp[i * R2 * P + jj];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NI; ++i) dftR<T, INV, R2>(&d[i * R2]);
+}
+
+// Inverse of line_fft_t (unnormalised): back to d[m] = len x[j + R2 m].
+template <typename T, int R1, int R2>
+__device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti) {
+  constexpr int NI = R1 / R2, P = LineX<R1, R2>::P;
+  C<T>* wp = line + j * P;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    dftR<T, true, R2>(&d[i * R2]);
+    const C<T>* w = ti + (j + R2 * i) * R2;
+#pragma unroll
+    for (int jj = 0; jj < R2; ++jj) {
+      C<T> v = d[i * R2 + jj];
+      if (jj) v = cmulc(v, w[jj]);
+      wp[i * R2 * P + jj] = v;
+    }
+  }
+  __syncthreads();
+  const C<T>* rp = line + j;
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) d[k1] = rp[k1 * P];
+  __syncthreads();
+  dftR<T, true, R1>(d);
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access: a resource per workgroup-uniform slice, a per-thread
+// byte offset and a compile-time (scalar) byte offset per access, so that a
+// strided sweep costs no vector address arithmetic.  Word 3 of the resource
+// is the gfx9-family raw (untyped, 32-bit) format; accesses past `bytes`
+// read zero and drop writes.
+// ---------------------------------------------------------------------------
+using brsrc = __amdgpu_buffer_rsrc_t;
+__device__ inline brsrc make_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(uint32_t)bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline C<T> bload(brsrc r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
+}
+template <typename T>
+__device__ inline void bstore(C<T> v, brsrc r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+  } else {
+    using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, voff, soff, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Reductions (FP64, deterministic order).
 // ---------------------------------------------------------------------------
 __device__ inline double wave_sum(double v) {

@@ -13,6 +13,7 @@ struct bq_ctx {
   bq_geom g{};
   int L = 0;
   std::vector<bq_illum> dirs;
+  std::vector<bq::C<double>> inc_tab;  // plane-wave factors per illumination, L x 3 x N
   hipStream_t stream = nullptr;
   std::string err;
   double kb = 0.0;

@@ -2,14 +2,18 @@
 //
 // Same passes and data layout as the LDS-Stockham passes of green.hip, but
 // for the strided lines (z forward with prologue, y transfer-function
-// convolution, z inverse with epilogue) every N-point line transform is held
-// in registers by R2 threads (R1 points each) with a single exchange through
+// convolution, z inverse with epilogue) every line transform is held in
+// registers by R2 threads (R1 points each) with a single exchange through
 // LDS, which cuts LDS traffic about fourfold.  The x passes keep the
 // Stockham kernels (whole contiguous rows per access measured faster).
 //
 // Lane mapping: consecutive lanes take consecutive lines, so global
-// accesses are coalesced along x and the LDS exchange (line stride N + 1) is
-// conflict free.
+// accesses are coalesced along x; the exchange layout and the per-thread
+// twiddle rows of line_fft_t make every LDS access a base address plus a
+// constant offset (no bank conflicts measured).  The strided sweeps of the y
+// pass and of the transform sides of the z passes are raw buffer accesses
+// with the stride in the scalar offset, which keeps address arithmetic off
+// the vector ALU -- the y pass is bound by vector-ALU issue.
 #include "bq_kernels.h"
 
 namespace bq {
@@ -162,17 +166,30 @@ __device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, 
   }
 }
 
+// Twiddle tables of line_fft_t / line_ifft_t for N-point lines: W_N^n from
+// the table exp(-2 pi i n / N), n < N.
+template <typename T, int R1, int R2>
+__device__ inline void load_twtab_n(C<T>* t, const C<T>* twN, int tid) {
+  for (int e = tid; e < R1 * R2; e += RT) {
+    const int a = e / R1, b = e - a * R1;
+    const C<T> v = twN[a * b];
+    t[e] = v;
+    if constexpr (R1 != R2) t[R1 * R2 + b * R2 + a] = v;
+  }
+}
+
 // z lines.  Line L = y N + x of the N^2 lines; element z at z N^2 + L.
 // grid (N^2 / LPW, 1, B)
 template <typename T, int N>
 __global__ void __launch_bounds__(RT) k_zf_r(PassArgs<T> a) {
-  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = RT / R2, LS = N + 1, NI = R1 / R2;
+  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = RT / R2, LS = LineX<R1, R2>::LS, NI = R1 / R2;
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> tw[N];
+  __shared__ C<T> twt[LineX<R1, R2>::TW];
   __shared__ C<T> th[N];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  for (int i = tid; i < N; i += RT) { tw[i] = a.twN[i]; th[i] = a.twH[i]; }
+  load_twtab_n<T, R1, R2>(twt, a.twN, tid);
+  for (int i = tid; i < N; i += RT) th[i] = a.twH[i];
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
   C<T> orig[R1], d[R1];
@@ -181,7 +198,7 @@ __global__ void __launch_bounds__(RT) k_zf_r(PassArgs<T> a) {
   for (int pz = 0; pz < 2; ++pz) {
 #pragma unroll
     for (int m = 0; m < R1; ++m) d[m] = pz ? cmul(orig[m], th[j + R2 * m]) : orig[m];
-    line_fft<T, N, R1, R2, false>(d, &lds[line * LS], 1, j, tw);
+    line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
     C<T>* dst = a.zh + (size_t)(b * 2 + pz) * V + L;
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -197,14 +214,15 @@ __global__ void __launch_bounds__(RT) k_zf_r(PassArgs<T> a) {
 // (kz N + y) N + kx.  grid (N^2 / LPW, 1, 4 B)
 template <typename T, int N>
 __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
-  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = RT / R2, LS = N + 1, NI = R1 / R2;
+  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = RT / R2, LS = LineX<R1, R2>::LS, NI = R1 / R2;
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> tw[N];
+  __shared__ C<T> twt[LineX<R1, R2>::TW];
   __shared__ C<T> th[N];
   const int b = blockIdx.z >> 2, cls = blockIdx.z & 3, pz = cls >> 1, px = cls & 1;
   const int tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  for (int i = tid; i < N; i += RT) { tw[i] = a.twN[i]; th[i] = a.twH[i]; }
+  load_twtab_n<T, R1, R2>(twt, a.twN, tid);
+  for (int i = tid; i < N; i += RT) th[i] = a.twH[i];
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
   const int kz = L / N, kx = L - kz * N;
@@ -219,7 +237,7 @@ __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
   for (int py = 0; py < 2; ++py) {
 #pragma unroll
     for (int m = 0; m < R1; ++m) d[m] = py ? cmul(orig[m], th[j + R2 * m]) : orig[m];
-    line_fft<T, N, R1, R2, false>(d, &lds[line * LS], 1, j, tw);
+    line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
     const C<T>* g = a.ghat + (size_t)((pz * 2 + py) * 2 + px) * V + (size_t)kz * N2 + kx;
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -228,7 +246,7 @@ __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
         const int ky = (j + R2 * i) + R1 * k2;
         d[i * R2 + k2] = cmul(d[i * R2 + k2], g[(size_t)ky * N]);
       }
-    line_ifft<T, N, R1, R2>(d, &lds[line * LS], 1, j, tw);
+    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
 #pragma unroll
     for (int m = 0; m < R1; ++m) acc[m] = acc[m] + (py ? cmulc(d[m], th[j + R2 * m]) : d[m]);
   }
@@ -240,14 +258,15 @@ __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
 // grid (N^2 / LPW, 1, B); partials[(b * NP + blockIdx.x) * 4 + k]
 template <typename T, int N>
 __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
-  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = RT / R2, LS = N + 1, NI = R1 / R2;
+  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = RT / R2, LS = LineX<R1, R2>::LS, NI = R1 / R2;
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> tw[N];
+  __shared__ C<T> twt[LineX<R1, R2>::TW];
   __shared__ C<T> th[N];
   __shared__ double red_scratch[(RT / 64) * 3];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  for (int i = tid; i < N; i += RT) { tw[i] = a.twN[i]; th[i] = a.twH[i]; }
+  load_twtab_n<T, R1, R2>(twt, a.twN, tid);
+  for (int i = tid; i < N; i += RT) th[i] = a.twH[i];
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
   C<T> acc[R1], d[R1];
@@ -260,7 +279,7 @@ __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
     for (int i = 0; i < NI; ++i)
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) d[i * R2 + k2] = src[(size_t)((j + R2 * i) + R1 * k2) * N2];
-    line_ifft<T, N, R1, R2>(d, &lds[line * LS], 1, j, tw);
+    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
 #pragma unroll
     for (int m = 0; m < R1; ++m) acc[m] = acc[m] + (pz ? cmulc(d[m], th[j + R2 * m]) : d[m]);
   }
@@ -304,24 +323,29 @@ BQ_PC(64, 16, 8)
 BQ_PC(128, 16, 16)
 #undef BQ_PC
 
-// W_{2N}^k for k < 2N from the half-angle table exp(-i pi n / N), n < N
-template <typename T, int N>
-__device__ inline void load_tw2(C<T>* tw2, const C<T>* twH, int tid) {
-  for (int i = tid; i < 2 * N; i += RT) {
-    const C<T> w = twH[i < N ? i : i - N];
-    tw2[i] = i < N ? w : C<T>{-w.x, -w.y};
+// Twiddle tables of line_fft_t / line_ifft_t for the padded 2N-point lines:
+// W_{2N}^n = exp(-i pi n / N) from the half-angle table (n < 2N).
+template <typename T, int N, int R1, int R2>
+__device__ inline void load_twtab_pad(C<T>* t, const C<T>* twH, int tid) {
+  for (int e = tid; e < R1 * R2; e += RT) {
+    const int a = e / R1, b = e - a * R1, n = a * b;
+    const C<T> w = twH[n < N ? n : n - N];
+    const C<T> v = n < N ? w : C<T>{-w.x, -w.y};
+    t[e] = v;
+    if constexpr (R1 != R2) t[R1 * R2 + b * R2 + a] = v;
   }
 }
 
 template <typename T, int N>
 __global__ void __launch_bounds__(RT) k_zf_p(PassArgs<T> a) {
-  constexpr int M = 2 * N, R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, LS = M + 1, NI = R1 / R2;
-  constexpr int H = R1 / 2;  // nonzero inputs per thread
+  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, NI = R1 / R2;
+  constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;  // H: nonzero inputs per thread
+  constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> tw2[M];
+  __shared__ C<T> twt[LineX<R1, R2>::TW];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_tw2<T, N>(tw2, a.twH, tid);
+  load_twtab_pad<T, N, R1, R2>(twt, a.twH, tid);
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
   C<T> d[R1];
@@ -329,23 +353,26 @@ __global__ void __launch_bounds__(RT) k_zf_p(PassArgs<T> a) {
 #pragma unroll
   for (int m = H; m < R1; ++m) d[m] = C<T>{0, 0};
   __syncthreads();  // twiddle table
-  line_fft<T, M, R1, R2, false>(d, &lds[line * LS], 1, j, tw2);
+  line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
+  // padded frequency kp = k1 + R1 k2 (k1 = j + R2 i): class kp & 1 = j & 1,
+  // plane kp >> 1; the two classes of system b are consecutive volumes
+  const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * V, 2 * V * SZ);
+  const uint32_t vo = (uint32_t)((j & 1) * N * N * N + (j >> 1) * N * N + L) * SZ;
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      const int kp = (j + R2 * i) + R1 * k2;  // padded frequency
-      a.zh[(size_t)(b * 2 + (kp & 1)) * V + (size_t)(kp >> 1) * N2 + L] = d[i * R2 + k2];
-    }
+    for (int k2 = 0; k2 < R2; ++k2)
+      bstore<T>(d[i * R2 + k2], rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
 }
 
 // y columns of class (pz, px), line L = kz N + kx
 template <typename T, int N>
 __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
-  constexpr int M = 2 * N, R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, LS = M + 1, NI = R1 / R2;
-  constexpr int H = R1 / 2;
+  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, NI = R1 / R2;
+  constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;
+  constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> tw2[M];
+  __shared__ C<T> twt[LineX<R1, R2>::TW];
   // XCD-aware order: workgroup h runs on XCD h mod 8; the B systems of one
   // (class, line block) take consecutive slots of the same XCD, so the
   // transfer-function slab they share is fetched into that XCD's L2 once.
@@ -356,54 +383,55 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   const int cls = q / NLB, lb = q - cls * NLB, pz = cls >> 1, px = cls & 1;
   const int tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_tw2<T, N>(tw2, a.twH, tid);
+  load_twtab_pad<T, N, R1, R2>(twt, a.twH, tid);
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = lb * LPW + line;
   const int kz = L / N, kx = L - kz * N;
-  C<T>* col = a.xh + ((size_t)b * 4 + cls) * V + (size_t)kz * N2 + kx;
+  // column: one resource per (system, class) slice, element y at (kz N + y) N + kx
+  const brsrc rc = make_rsrc(a.xh + ((size_t)b * 4 + cls) * V, V * SZ);
+  const uint32_t vo = (uint32_t)(kz * N * N + kx + j * N) * SZ;
   C<T> d[R1];
 #pragma unroll
-  for (int m = 0; m < R1; ++m) d[m] = (m < H) ? col[(size_t)(j + R2 * m) * N] : C<T>{0, 0};
+  for (int m = 0; m < R1; ++m) d[m] = (m < H) ? bload<T>(rc, vo, (uint32_t)(m * R2 * N) * SZ) : C<T>{0, 0};
+  // padded frequency kp = k1 + R1 k2 (k1 = j + R2 i) is py class kp & 1 = j & 1
+  // at index kp >> 1; classes (pz, 0, px) and (pz, 1, px) are 2V apart
+  const brsrc rg = make_rsrc(a.ghat + (size_t)(pz * 4 + px) * V, 3 * V * SZ);
+  const uint32_t vg = (uint32_t)((j & 1) * 2 * N * N * N + kz * N * N + kx + (j >> 1) * N) * SZ;
   __syncthreads();
-  line_fft<T, M, R1, R2, false>(d, &lds[line * LS], 1, j, tw2);
-  const C<T>* g0 = a.ghat + (size_t)((pz * 2 + 0) * 2 + px) * V + (size_t)kz * N2 + kx;
-  const C<T>* g1 = a.ghat + (size_t)((pz * 2 + 1) * 2 + px) * V + (size_t)kz * N2 + kx;
+  line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      const int kp = (j + R2 * i) + R1 * k2;
-      const C<T>* g = (kp & 1) ? g1 : g0;
-      d[i * R2 + k2] = cmul(d[i * R2 + k2], g[(size_t)(kp >> 1) * N]);
-    }
-  line_ifft<T, M, R1, R2>(d, &lds[line * LS], 1, j, tw2);
+    for (int k2 = 0; k2 < R2; ++k2)
+      d[i * R2 + k2] = cmul(d[i * R2 + k2], bload<T>(rg, vg, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N) * SZ));
+  line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
 #pragma unroll
-  for (int m = 0; m < H; ++m) col[(size_t)(j + R2 * m) * N] = d[m];
+  for (int m = 0; m < H; ++m) bstore<T>(d[m], rc, vo, (uint32_t)(m * R2 * N) * SZ);
 }
 
 // z lines, inverse (first N outputs of the padded inverse), epilogue
 template <typename T, int N>
 __global__ void __launch_bounds__(RT) k_zi_p(PassArgs<T> a) {
-  constexpr int M = 2 * N, R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, LS = M + 1, NI = R1 / R2;
-  constexpr int H = R1 / 2;
+  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, NI = R1 / R2;
+  constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;
+  constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> tw2[M];
+  __shared__ C<T> twt[LineX<R1, R2>::TW];
   __shared__ double red_scratch[(RT / 64) * 3];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_tw2<T, N>(tw2, a.twH, tid);
-  const size_t N2 = (size_t)N * N, V = N2 * N;
+  load_twtab_pad<T, N, R1, R2>(twt, a.twH, tid);
   const int L = blockIdx.x * LPW + line;
+  const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * N * N * N, 2 * (size_t)N * N * N * SZ);
+  const uint32_t vo = (uint32_t)((j & 1) * N * N * N + (j >> 1) * N * N + L) * SZ;
   C<T> d[R1];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      const int kp = (j + R2 * i) + R1 * k2;
-      d[i * R2 + k2] = a.zh[(size_t)(b * 2 + (kp & 1)) * V + (size_t)(kp >> 1) * N2 + L];
-    }
+    for (int k2 = 0; k2 < R2; ++k2)
+      d[i * R2 + k2] = bload<T>(rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
   __syncthreads();
-  line_ifft<T, M, R1, R2>(d, &lds[line * LS], 1, j, tw2);
+  line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
   double red[3] = {0.0, 0.0, 0.0};
   const int mode = a.zi_mode;
   zi_epilogue<T, N, R2, H>(a, b, j, L, d, red);
