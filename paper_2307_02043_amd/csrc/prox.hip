@@ -49,7 +49,7 @@ struct ProxState {
   int max_passes_seen;
   int has_u, nonneg;
   int gaveup;         // dual iterations whose root was not pinned down
-  int pad_;
+  int overflow;       // a dual iteration needed more root passes than were launched
   double eps;         // unit roundoff of the image precision
   double t, mom;      // FISTA sequence t_k and the momentum (t_k - 1) / t_{k+1}
 };
@@ -77,7 +77,9 @@ __device__ inline T xval(const ProxArgs<T>& a, size_t i, T theta, bool nonneg, b
   return nonneg ? (w > T(0) ? w : T(0)) : w;
 }
 
-// a = v - (lambda / tau) d(R); partials: u.d, u.a, S_A(theta0), T_A(theta0)
+// a = v - (lambda / tau) d(R); partials: u.d, u.a, S_A(theta0), T_A(theta0).
+// Rows (z, y) over workgroups, x over threads; two rows per step with all
+// their loads issued before any arithmetic, to keep enough bytes in flight.
 template <typename T>
 __global__ void __launch_bounds__(PX_WG) k_div(ProxArgs<T> p) {
   __shared__ double scratch[(PX_WG / 64) * 4];
@@ -89,32 +91,47 @@ __global__ void __launch_bounds__(PX_WG) k_div(ProxArgs<T> p) {
   const T* Rz = p.R;
   const T* Ry = p.R + V;
   const T* Rx = p.R + 2 * V;
-  // rows (z, y) over workgroups, x over threads: one division per row
   const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
-  for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x) {
+  // (D^a)^T q at i: q[i - e_a] (if i_a > 0) - q[i] (if i_a < n_a - 1)
+  auto divergence = [&](unsigned row, int x) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
-    const size_t base = (size_t)row * p.nx;
-    for (int x = threadIdx.x; x < p.nx; x += PX_WG) {
-      const size_t i = base + x;
-      T d = 0;
-      // (D^a)^T q at i: q[i - e_a] (if i_a > 0) - q[i] (if i_a < n_a - 1)
-      if (z > 0) d += Rz[i - sz];
-      if (z < p.nz - 1) d -= Rz[i];
-      if (y > 0) d += Ry[i - sy];
-      if (y < p.ny - 1) d -= Ry[i];
-      if (x > 0) d += Rx[i - 1];
-      if (x < p.nx - 1) d -= Rx[i];
-      const T av = p.v[i] - (T)lt * d;
-      p.a[i] = av;
-      if (s.has_u) {
-        const T uv = p.u[i];
-        acc[0] += (double)uv * d;
-        acc[1] += (double)uv * av;
-        if (av - uv * theta0 > T(0)) {
-          acc[2] += (double)uv * uv;
-          acc[3] += (double)uv * av;
-        }
+    const size_t i = (size_t)row * p.nx + x;
+    T d = 0;
+    if (z > 0) d += Rz[i - sz];
+    if (z < p.nz - 1) d -= Rz[i];
+    if (y > 0) d += Ry[i - sy];
+    if (y < p.ny - 1) d -= Ry[i];
+    if (x > 0) d += Rx[i - 1];
+    if (x < p.nx - 1) d -= Rx[i];
+    return d;
+  };
+  auto finish = [&](size_t i, T d, T vv, T uv) {
+    const T av = vv - (T)lt * d;
+    p.a[i] = av;
+    if (s.has_u) {
+      acc[0] += (double)uv * d;
+      acc[1] += (double)uv * av;
+      if (av - uv * theta0 > T(0)) {
+        acc[2] += (double)uv * uv;
+        acc[3] += (double)uv * av;
       }
+    }
+  };
+  for (unsigned row0 = blockIdx.x; row0 < nrows; row0 += 2 * gridDim.x) {
+    const unsigned row1 = row0 + gridDim.x;
+    const bool two = row1 < nrows;
+    for (int x = threadIdx.x; x < p.nx; x += PX_WG) {
+      const size_t i0 = (size_t)row0 * p.nx + x, i1 = (size_t)row1 * p.nx + x;
+      const T d0 = divergence(row0, x);
+      const T v0 = p.v[i0], u0 = s.has_u ? p.u[i0] : T(0);
+      T d1 = 0, v1 = 0, u1 = 0;
+      if (two) {
+        d1 = divergence(row1, x);
+        v1 = p.v[i1];
+        u1 = s.has_u ? p.u[i1] : T(0);
+      }
+      finish(i0, d0, v0, u0);
+      if (two) finish(i1, d1, v1, u1);
     }
   }
   if (!s.has_u) return;
@@ -232,7 +249,10 @@ __global__ void __launch_bounds__(256) k_px_after_div(ProxState* st, const doubl
   *st = s;
 }
 
-__global__ void __launch_bounds__(256) k_px_after_ssn(ProxState* st, const double* part, int np, int max_passes) {
+// last_slot: no further pass follows in this dual iteration; a root still
+// open there is flagged (the host then reruns with every pass launched)
+__global__ void __launch_bounds__(256) k_px_after_ssn(ProxState* st, const double* part, int np, int max_passes,
+                                                      int last_slot) {
   __shared__ double scratch[4 * 2];
   if (st->done) return;
   double v[2];
@@ -240,6 +260,10 @@ __global__ void __launch_bounds__(256) k_px_after_ssn(ProxState* st, const doubl
   if (threadIdx.x != 0) return;
   ProxState s = *st;
   px_step(s, v[0], v[1], max_passes);
+  if (last_slot && !s.done) {
+    s.overflow = 1;
+    s.done = 1;
+  }
   *st = s;
 }
 
@@ -347,15 +371,12 @@ int px_grid(size_t V) {
   return (int)g;
 }
 
+// One run of the iteration with `slots` root passes launched per dual
+// iteration; the final device state goes to *hs.
 template <typename T>
-bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
-                    int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
+bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
+                         int n_iter, void* x_out, void* P_io, int slots, ProxState* hs_out) {
   const size_t V = p->V;
-  // order after the caller's pending work, then run on the library stream
-  if (hipEventRecord(p->ev, p->stream) != hipSuccess || hipStreamWaitEvent(p->own, p->ev, 0) != hipSuccess) {
-    p->err = "stream synchronisation failed";
-    return BQ_EDEVICE;
-  }
   const hipStream_t s = p->own;
   const dim3 g(p->np), b(PX_WG);
   ProxArgs<T> a{};
@@ -383,7 +404,7 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
     p->err = "copy of the starting dual point failed";
     return BQ_EDEVICE;
   }
-  const int max_launch = (has_u && nonneg) ? p->max_passes - 1 : 0;  // SSN passes per dual iteration
+  const int max_launch = (has_u && nonneg) ? slots : 0;  // SSN passes per dual iteration
   // divergence + root finding for the current momentum R (all arguments are
   // iteration invariant: the momentum coefficient lives on the device)
   auto primal = [&]() {
@@ -393,7 +414,7 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
     for (int j = 0; j < max_launch; ++j) {
       hipLaunchKernelGGL((k_ssn<T>), g, b, 0, s, a);
       hipLaunchKernelGGL(k_px_after_ssn, dim3(1), dim3(256), 0, s, p->st, (const double*)p->partial, p->np,
-                         p->max_passes);
+                         p->max_passes, j == max_launch - 1 ? 1 : 0);
     }
   };
   if (n_iter > 0) {
@@ -427,12 +448,32 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
     p->err = "kernel launch failed";
     return BQ_EDEVICE;
   }
-  ProxState hs{};
-  if (hipMemcpyAsync(&hs, p->st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(hs_out, p->st, sizeof(ProxState), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     p->err = "device error in the proximal mapping";
     return BQ_EDEVICE;
   }
+  return BQ_OK;
+}
+
+template <typename T>
+bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
+                    int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
+  // order after the caller's pending work, then run on the library stream
+  if (hipEventRecord(p->ev, p->stream) != hipSuccess || hipStreamWaitEvent(p->own, p->ev, 0) != hipSuccess) {
+    p->err = "stream synchronisation failed";
+    return BQ_EDEVICE;
+  }
+  ProxState hs{};
+  const bq_status st = run_with_pass_budget(
+      p, P_io, 3 * p->V * sizeof(T), u != nullptr && cset == BQ_SET_NONNEG, p->ssn_slots, p->max_passes - 1,
+      [&](int slots, int* overflow, int* seen) {
+        const bq_status r = run_wprox_once<T>(p, v, tau, u, lam, tv, cset, n_iter, x_out, P_io, slots, &hs);
+        *overflow = hs.overflow;
+        *seen = hs.max_passes_seen;
+        return r;
+      });
+  if (st != BQ_OK) return st;
   if (stats) {
     stats->newton_total = hs.total_passes;
     stats->newton_max = hs.max_passes_seen;
@@ -448,7 +489,7 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
 
 void free_prox(bq_prox* p) {
   if (!p) return;
-  void* ptrs[] = {p->a, p->P, p->R, p->xbuf, p->partial, p->st, p->rst};
+  void* ptrs[] = {p->a, p->P, p->R, p->xbuf, p->partial, p->st, p->rst, p->Pbak};
   for (void* q : ptrs) if (q) (void)hipFree(q);
   if (p->ev) (void)hipEventDestroy(p->ev);
   if (p->own) (void)hipStreamDestroy(p->own);

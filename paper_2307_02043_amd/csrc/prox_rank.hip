@@ -47,6 +47,7 @@ struct ProxRankState {
   double thk[RM], gk[RM], dir[RM];
   double psik, step, slope_k, phi_max, dmax_k;
   int r, nonneg, done, passes, total_passes, max_passes_seen, gaveup, have_k;
+  int overflow;  // a dual iteration needed more root passes than were launched
 };
 
 template <int R>
@@ -386,9 +387,11 @@ __global__ void __launch_bounds__(256) k_pr_after_div(ProxRankState* st, const d
   pr_eval<R>(s, &v[K_::S], &v[K_::T], v[K_::Q], max_passes);
 }
 
+// last_slot: no further pass follows in this dual iteration; a root still
+// open there is flagged (the host then reruns with every pass launched)
 template <int R>
 __global__ void __launch_bounds__(256) k_pr_after_ssn(ProxRankState* st, const double* part, int np,
-                                                      int max_passes) {
+                                                      int max_passes, int last_slot) {
   using K_ = RK<R>;
   constexpr int KS = K_::K - K_::S;
   __shared__ double scratch[4 * KS];
@@ -397,6 +400,10 @@ __global__ void __launch_bounds__(256) k_pr_after_ssn(ProxRankState* st, const d
   pr_sum<K_::S, KS>(part, np, v, scratch);
   if (threadIdx.x != 0) return;
   pr_eval<R>(*st, &v[0], &v[K_::NS], v[K_::NS + R], max_passes);
+  if (last_slot && !st->done) {
+    st->overflow = 1;
+    st->done = 1;
+  }
 }
 
 // x = max(a - U theta, 0) (or a - U theta without the constraint)
@@ -482,14 +489,12 @@ static int pr_grid(size_t V) {
   return (int)g;
 }
 
+// One run of the iteration with `slots` root passes launched per dual
+// iteration; the final device state goes to *hs_out.
 template <typename T, int R>
-static bq_status run_rank(bq_prox* p, const void* v, double tau, const void* U, double lam, int tv, int cset,
-                          int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
+static bq_status run_rank_once(bq_prox* p, const void* v, double tau, const void* U, double lam, int tv,
+                               int cset, int n_iter, void* x_out, void* P_io, int slots, ProxRankState* hs_out) {
   const size_t V = p->V;
-  if (hipEventRecord(p->ev, p->stream) != hipSuccess || hipStreamWaitEvent(p->own, p->ev, 0) != hipSuccess) {
-    p->err = "stream synchronisation failed";
-    return BQ_EDEVICE;
-  }
   const hipStream_t s = p->own;
   const int np = pr_grid(V);
   if (np > p->np) {
@@ -520,14 +525,14 @@ static bq_status run_rank(bq_prox* p, const void* v, double tau, const void* U, 
     return BQ_EDEVICE;
   }
   const int mp = p->max_passes_rank;
-  const int n_ssn = nonneg ? mp - 1 : 0;
+  const int n_ssn = nonneg ? slots : 0;
   auto primal = [&](T* xdst) {
     hipLaunchKernelGGL((k_div_r<T, R>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_pr_after_div<R>), dim3(1), dim3(256), 0, s, p->rst, (const double*)p->partial, np, mp);
     for (int j = 0; j < n_ssn; ++j) {
       hipLaunchKernelGGL((k_ssn_r<T, R>), g, b, 0, s, a);
       hipLaunchKernelGGL((k_pr_after_ssn<R>), dim3(1), dim3(256), 0, s, p->rst, (const double*)p->partial, np,
-                         mp);
+                         mp, j == n_ssn - 1 ? 1 : 0);
     }
     hipLaunchKernelGGL((k_xr<T, R>), g, b, 0, s, a, xdst);
   };
@@ -559,12 +564,31 @@ static bq_status run_rank(bq_prox* p, const void* v, double tau, const void* U, 
     p->err = "kernel launch failed";
     return BQ_EDEVICE;
   }
-  ProxRankState hs{};
-  if (hipMemcpyAsync(&hs, p->rst, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(hs_out, p->rst, sizeof(ProxRankState), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     p->err = "device error in the proximal mapping";
     return BQ_EDEVICE;
   }
+  return BQ_OK;
+}
+
+template <typename T, int R>
+static bq_status run_rank(bq_prox* p, const void* v, double tau, const void* U, double lam, int tv, int cset,
+                          int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
+  if (hipEventRecord(p->ev, p->stream) != hipSuccess || hipStreamWaitEvent(p->own, p->ev, 0) != hipSuccess) {
+    p->err = "stream synchronisation failed";
+    return BQ_EDEVICE;
+  }
+  ProxRankState hs{};
+  const bq_status st = run_with_pass_budget(
+      p, P_io, 3 * p->V * sizeof(T), cset == BQ_SET_NONNEG, p->ssn_slots_rank, p->max_passes_rank - 1,
+      [&](int slots, int* overflow, int* seen) {
+        const bq_status r = run_rank_once<T, R>(p, v, tau, U, lam, tv, cset, n_iter, x_out, P_io, slots, &hs);
+        *overflow = hs.overflow;
+        *seen = hs.max_passes_seen;
+        return r;
+      });
+  if (st != BQ_OK) return st;
   if (stats) {
     stats->newton_total = hs.total_passes;
     stats->newton_max = hs.max_passes_seen;

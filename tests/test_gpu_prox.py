@@ -226,3 +226,47 @@ def test_wprox_rank_r_rejects_bad_rank_and_replays_stably(dev):
             assert torch.equal(y, first), rep
         del junk
     px.close()
+
+
+def test_wprox_root_pass_budget_rerun(dev):
+    """A call first launches two root passes per dual iteration; the cold start
+    of this input needs four evaluations, so the call runs again with the full
+    pass budget.  The result matches the oracle, a second call on the same
+    object (which keeps the larger budget) gives the same bits, and a caller's
+    starting dual point is restored before the rerun."""
+    from paper_2307_02043_amd import WProx
+    shape = (12, 14, 10)
+    rng = np.random.default_rng(5)
+    v = 0.02 * rng.standard_normal(shape) + 0.002 * rng.random(shape)
+    u = 0.1 * rng.standard_normal(shape)
+    ref, Pref = tp.wprox(v, 0.8, u, 1e-3, "iso", "nonneg", n_iter=20, return_dual=True)
+    vt, ut = torch.from_numpy(v).to(dev), torch.from_numpy(u).to(dev)
+    px = WProx(shape, "f64")
+    x1, i1 = px(vt, 0.8, ut, 1e-3, "iso", "nonneg", 20)
+    assert i1.newton_max >= 4, i1
+    x2, i2 = px(vt, 0.8, ut, 1e-3, "iso", "nonneg", 20)
+    assert torch.equal(x1, x2) and i2.newton_total == i1.newton_total
+    assert _rel(x1.cpu().numpy(), ref) < 1e-10
+    px.close()
+    px = WProx(shape, "f64")
+    P = torch.zeros((3,) + shape, dtype=torch.float64, device=dev)
+    x3, _ = px(vt, 0.8, ut, 1e-3, "iso", "nonneg", 20, P=P)
+    assert torch.equal(x3, x1)
+    assert _rel(P.cpu().numpy(), Pref) < 1e-10
+    px.close()
+
+
+def test_wprox_rank_r_pass_budget_is_transparent(dev):
+    """Rank 3: calls on a fresh object and on one that already raised its root
+    pass budget agree bit for bit and match the oracle."""
+    from paper_2307_02043_amd import WProx
+    shape = (13, 17, 19)
+    v, U = _inputs_rank(shape, 3, 21)
+    ref = tp.wprox(v, 0.8, U, 2e-3, "aniso", "nonneg", n_iter=25)
+    vt, Ut = torch.from_numpy(v).to(dev), torch.from_numpy(U).to(dev)
+    px = WProx(shape, "f64")
+    x1, i1 = px(vt, 0.8, Ut, 2e-3, "aniso", "nonneg", 25)
+    x2, i2 = px(vt, 0.8, Ut, 2e-3, "aniso", "nonneg", 25)
+    assert torch.equal(x1, x2) and i1.newton_total == i2.newton_total
+    assert _rel(x1.cpu().numpy(), ref) < 1e-10
+    px.close()
