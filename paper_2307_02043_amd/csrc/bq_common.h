@@ -391,17 +391,39 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum K values over the workgroup; result valid in thread 0.  scratch must
-// hold (NTHR / 64) * K doubles.
+constexpr int clog2(int k) { return k <= 1 ? 0 : 1 + clog2((k + 1) / 2); }
+
+// Sum K <= 64 values over the workgroup; result valid in thread 0.  scratch
+// must hold (NTHR / 64) * K doubles.  Within a wave the sums form a
+// reduce-scatter: each halving step keeps half of the values a lane still
+// holds and exchanges the other half with the partner lane, so a wave pays
+// about K shuffles instead of K log2(64).  Afterwards the lanes l with
+// l mod 2^(6-M) == 0 hold the wave total of value l >> (6 - M), M =
+// ceil(log2 K).  The order of every sum depends on lane and wave indices
+// only, so results are reproducible.
 template <int NTHR, int K>
 __device__ inline void block_sum(double* vals, double* scratch) {
+  static_assert(K >= 1 && K <= 64, "block_sum: 1..64 values");
+  constexpr int M = clog2(K), KP = 1 << M, SH = 6 - M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double v[KP];
 #pragma unroll
-  for (int k = 0; k < K; ++k) vals[k] = wave_sum(vals[k]);
-  if (lane == 0) {
+  for (int k = 0; k < KP; ++k) v[k] = k < K ? vals[k] : 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) scratch[wave * K + k] = vals[k];
+  for (int s = 0; s < M; ++s) {
+    const int o = 32 >> s, h = KP >> (s + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const double keep = up ? v[h + k] : v[k];
+      const double send = up ? v[k] : v[h + k];
+      v[k] = keep + __shfl_xor(send, o, 64);
+    }
   }
+  double t = v[0];
+#pragma unroll
+  for (int o = 32 >> M; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if ((lane & ((1 << SH) - 1)) == 0 && (lane >> SH) < K) scratch[wave * K + (lane >> SH)] = t;
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
