@@ -353,6 +353,50 @@ __device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti) {
 }
 
 // ---------------------------------------------------------------------------
+// Row-wise traversal of an image with nrows rows (z, y) of nx points: rows
+// over workgroups, x over threads.  When a row is shorter than the
+// workgroup, one step covers rps = WG / nx rows (thread t takes row t / nx of
+// the step at x = t mod nx; threads beyond rps rows idle).  Long rows keep
+// the row index workgroup-uniform (scalar index arithmetic and branches).
+// f(row0, row1, two, x) gets a pair of rows, row1 = row0 + the stride of
+// the traversal, two = row1 exists; for_rows hands single rows to f(row, x).
+// ---------------------------------------------------------------------------
+template <int WG, class F>
+__device__ inline void for_row_pairs(int nx, unsigned nrows, F&& f) {
+  if (nx >= WG) {
+    for (unsigned row0 = blockIdx.x; row0 < nrows; row0 += 2 * gridDim.x) {
+      const unsigned row1 = row0 + gridDim.x;
+      for (int x = threadIdx.x; x < nx; x += WG) f(row0, row1, row1 < nrows, x);
+    }
+  } else {
+    const unsigned rps = (unsigned)(WG / nx), rl = threadIdx.x / (unsigned)nx;
+    const int x = (int)(threadIdx.x - rl * (unsigned)nx);
+    const unsigned stride = gridDim.x * rps;
+    if (rl < rps)
+      for (unsigned rb = blockIdx.x * rps; rb < nrows; rb += 2 * stride) {
+        const unsigned row0 = rb + rl, row1 = row0 + stride;
+        if (row0 < nrows) f(row0, row1, row1 < nrows, x);
+      }
+  }
+}
+
+template <int WG, class F>
+__device__ inline void for_rows(int nx, unsigned nrows, F&& f) {
+  if (nx >= WG) {
+    for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x)
+      for (int x = threadIdx.x; x < nx; x += WG) f(row, x);
+  } else {
+    const unsigned rps = (unsigned)(WG / nx), rl = threadIdx.x / (unsigned)nx;
+    const int x = (int)(threadIdx.x - rl * (unsigned)nx);
+    if (rl < rps)
+      for (unsigned rb = blockIdx.x * rps; rb < nrows; rb += gridDim.x * rps) {
+        const unsigned row = rb + rl;
+        if (row < nrows) f(row, x);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Raw buffer access: a resource per workgroup-uniform slice, a per-thread
 // byte offset and a compile-time (scalar) byte offset per access, so that a
 // strided sweep costs no vector address arithmetic.  Word 3 of the resource

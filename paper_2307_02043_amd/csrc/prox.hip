@@ -117,23 +117,19 @@ __global__ void __launch_bounds__(PX_WG) k_div(ProxArgs<T> p) {
       }
     }
   };
-  for (unsigned row0 = blockIdx.x; row0 < nrows; row0 += 2 * gridDim.x) {
-    const unsigned row1 = row0 + gridDim.x;
-    const bool two = row1 < nrows;
-    for (int x = threadIdx.x; x < p.nx; x += PX_WG) {
-      const size_t i0 = (size_t)row0 * p.nx + x, i1 = (size_t)row1 * p.nx + x;
-      const T d0 = divergence(row0, x);
-      const T v0 = p.v[i0], u0 = s.has_u ? p.u[i0] : T(0);
-      T d1 = 0, v1 = 0, u1 = 0;
-      if (two) {
-        d1 = divergence(row1, x);
-        v1 = p.v[i1];
-        u1 = s.has_u ? p.u[i1] : T(0);
-      }
-      finish(i0, d0, v0, u0);
-      if (two) finish(i1, d1, v1, u1);
+  for_row_pairs<PX_WG>(p.nx, nrows, [&](unsigned row0, unsigned row1, bool two, int x) {
+    const size_t i0 = (size_t)row0 * p.nx + x, i1 = (size_t)row1 * p.nx + x;
+    const T d0 = divergence(row0, x);
+    const T v0 = p.v[i0], u0 = s.has_u ? p.u[i0] : T(0);
+    T d1 = 0, v1 = 0, u1 = 0;
+    if (two) {
+      d1 = divergence(row1, x);
+      v1 = p.v[i1];
+      u1 = s.has_u ? p.u[i1] : T(0);
     }
-  }
+    finish(i0, d0, v0, u0);
+    if (two) finish(i1, d1, v1, u1);
+  });
   if (!s.has_u) return;
   block_sum<PX_WG, 4>(acc, scratch);
   if (threadIdx.x == 0) {
@@ -295,36 +291,34 @@ __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
   const T sig = (T)p.sigma, mom = (T)stp->mom;
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
   const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
-  for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x) {
+  for_rows<PX_WG>(p.nx, nrows, [&](unsigned row, int x) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
     const size_t base = (size_t)row * p.nx;
-    for (int x = threadIdx.x; x < p.nx; x += PX_WG) {
-      const size_t i = base + x;
-      const T xc = xval(p, i, theta, nonneg, has_u);
-      const T gz = (z < p.nz - 1) ? xval(p, i + sz, theta, nonneg, has_u) - xc : T(0);
-      const T gy = (y < p.ny - 1) ? xval(p, i + sy, theta, nonneg, has_u) - xc : T(0);
-      const T gx = (x < p.nx - 1) ? xval(p, i + 1, theta, nonneg, has_u) - xc : T(0);
-      T qz = p.R[i] + sig * gz;
-      T qy = p.R[V + i] + sig * gy;
-      T qx = p.R[2 * V + i] + sig * gx;
-      if (p.iso) {
-        const T n = sqrt(qz * qz + qy * qy + qx * qx);
-        if (n > T(1)) {
-          const T inv = T(1) / n;
-          qz *= inv; qy *= inv; qx *= inv;
-        }
-      } else {
-        qz = fmin(fmax(qz, T(-1)), T(1));
-        qy = fmin(fmax(qy, T(-1)), T(1));
-        qx = fmin(fmax(qx, T(-1)), T(1));
+    const size_t i = base + x;
+    const T xc = xval(p, i, theta, nonneg, has_u);
+    const T gz = (z < p.nz - 1) ? xval(p, i + sz, theta, nonneg, has_u) - xc : T(0);
+    const T gy = (y < p.ny - 1) ? xval(p, i + sy, theta, nonneg, has_u) - xc : T(0);
+    const T gx = (x < p.nx - 1) ? xval(p, i + 1, theta, nonneg, has_u) - xc : T(0);
+    T qz = p.R[i] + sig * gz;
+    T qy = p.R[V + i] + sig * gy;
+    T qx = p.R[2 * V + i] + sig * gx;
+    if (p.iso) {
+      const T n = sqrt(qz * qz + qy * qy + qx * qx);
+      if (n > T(1)) {
+        const T inv = T(1) / n;
+        qz *= inv; qy *= inv; qx *= inv;
       }
-      const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
-      p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
-      p.R[i] = qz + mom * (qz - oz);
-      p.R[V + i] = qy + mom * (qy - oy);
-      p.R[2 * V + i] = qx + mom * (qx - ox);
+    } else {
+      qz = fmin(fmax(qz, T(-1)), T(1));
+      qy = fmin(fmax(qy, T(-1)), T(1));
+      qx = fmin(fmax(qx, T(-1)), T(1));
     }
-  }
+    const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
+    p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
+    p.R[i] = qz + mom * (qz - oz);
+    p.R[V + i] = qy + mom * (qy - oy);
+    p.R[2 * V + i] = qx + mom * (qx - ox);
+  });
 }
 
 template <typename T>

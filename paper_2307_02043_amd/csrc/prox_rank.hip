@@ -110,15 +110,16 @@ __device__ inline void chol_solve(const double* L, const double* b, double* x) {
   }
 }
 
-// Sum columns [K0, K0 + K) of the partials over the np workgroups (fixed
-// order); result in thread 0.
+// Partials are stored value-major: value k of workgroup b at k np + b, so
+// the reduction's loads are coalesced.  Sum values [K0, K0 + K) over the np
+// workgroups (fixed order); result in thread 0.
 template <int K0, int K>
 __device__ inline void pr_sum(const double* part, int np, double* out, double* scratch) {
 #pragma unroll
   for (int k = 0; k < K; ++k) out[k] = 0.0;
   for (int i = threadIdx.x; i < np; i += 256) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] += part[(size_t)i * PX_PART + K0 + k];
+    for (int k = 0; k < K; ++k) out[k] += part[(size_t)(K0 + k) * np + i];
   }
   block_sum<256, K>(out, scratch);
 }
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(PR_WG) k_gram_r(PRArgs<T> p) {
   block_sum<PR_WG, NS>(acc, scratch);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) p.partial[(size_t)blockIdx.x * PX_PART + k] = acc[k];
+    for (int k = 0; k < NS; ++k) p.partial[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
   }
 }
 
@@ -188,47 +189,44 @@ __global__ void __launch_bounds__(PR_WG) k_div_r(PRArgs<T> p) {
   const T* Rz = p.R;
   const T* Ry = p.R + V;
   const T* Rx = p.R + 2 * V;
-  // rows (z, y) over workgroups, x over threads: one division per row
   const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
-  for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x) {
+  for_rows<PR_WG>(p.nx, nrows, [&](unsigned row, int x) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
     const size_t base = (size_t)row * p.nx;
-    for (int x = threadIdx.x; x < p.nx; x += PR_WG) {
-      const size_t i = base + x;
-      T d = 0;
-      if (z > 0) d += Rz[i - sz];
-      if (z < p.nz - 1) d -= Rz[i];
-      if (y > 0) d += Ry[i - sy];
-      if (y < p.ny - 1) d -= Ry[i];
-      if (x > 0) d += Rx[i - 1];
-      if (x < p.nx - 1) d -= Rx[i];
-      const T av = p.v[i] - (T)lt * d;
-      p.a[i] = av;
-      T u[R];
+    const size_t i = base + x;
+    T d = 0;
+    if (z > 0) d += Rz[i - sz];
+    if (z < p.nz - 1) d -= Rz[i];
+    if (y > 0) d += Ry[i - sy];
+    if (y < p.ny - 1) d -= Ry[i];
+    if (x > 0) d += Rx[i - 1];
+    if (x < p.nx - 1) d -= Rx[i];
+    const T av = p.v[i] - (T)lt * d;
+    p.a[i] = av;
+    T u[R];
 #pragma unroll
-      for (int c = 0; c < R; ++c) u[c] = p.U[c * V + i];
-      T zr = av;
+    for (int c = 0; c < R; ++c) u[c] = p.U[c * V + i];
+    T zr = av;
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      acc[K_::C + c] += (double)u[c] * d;
+      acc[K_::UA + c] += (double)u[c] * av;
+      zr -= u[c] * th[c];
+    }
+    if (zr > T(0)) {
 #pragma unroll
       for (int c = 0; c < R; ++c) {
-        acc[K_::C + c] += (double)u[c] * d;
-        acc[K_::UA + c] += (double)u[c] * av;
-        zr -= u[c] * th[c];
-      }
-      if (zr > T(0)) {
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-#pragma unroll
-          for (int e = c; e < R; ++e) acc[K_::S + tri<R>(c, e)] += (double)u[c] * u[e];
-          acc[K_::T + c] += (double)u[c] * av;
-        }
-        acc[K_::Q] += (double)zr * zr;
+        for (int e = c; e < R; ++e) acc[K_::S + tri<R>(c, e)] += (double)u[c] * u[e];
+        acc[K_::T + c] += (double)u[c] * av;
       }
+      acc[K_::Q] += (double)zr * zr;
     }
-  }
+  });
   block_sum<PR_WG, K_::K>(acc, scratch);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K_::K; ++k) p.partial[(size_t)blockIdx.x * PX_PART + k] = acc[k];
+    for (int k = 0; k < K_::K; ++k) p.partial[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
   }
 }
 
@@ -267,7 +265,7 @@ __global__ void __launch_bounds__(PR_WG) k_ssn_r(PRArgs<T> p) {
   block_sum<PR_WG, KS>(acc, scratch);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < KS; ++k) p.partial[(size_t)blockIdx.x * PX_PART + K_::S + k] = acc[k];
+    for (int k = 0; k < KS; ++k) p.partial[(size_t)(K_::S + k) * gridDim.x + blockIdx.x] = acc[k];
   }
 }
 
@@ -428,36 +426,34 @@ __global__ void __launch_bounds__(PR_WG) k_dual_x(PRArgs<T> p) {
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
   const T* xb = p.xbuf;
   const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
-  for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x) {
+  for_rows<PR_WG>(p.nx, nrows, [&](unsigned row, int x) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
     const size_t base = (size_t)row * p.nx;
-    for (int x = threadIdx.x; x < p.nx; x += PR_WG) {
-      const size_t i = base + x;
-      const T xc = xb[i];
-      const T gz = (z < p.nz - 1) ? xb[i + sz] - xc : T(0);
-      const T gy = (y < p.ny - 1) ? xb[i + sy] - xc : T(0);
-      const T gx = (x < p.nx - 1) ? xb[i + 1] - xc : T(0);
-      T qz = p.R[i] + sig * gz;
-      T qy = p.R[V + i] + sig * gy;
-      T qx = p.R[2 * V + i] + sig * gx;
-      if (p.iso) {
-        const T n = sqrt(qz * qz + qy * qy + qx * qx);
-        if (n > T(1)) {
-          const T inv = T(1) / n;
-          qz *= inv; qy *= inv; qx *= inv;
-        }
-      } else {
-        qz = fmin(fmax(qz, T(-1)), T(1));
-        qy = fmin(fmax(qy, T(-1)), T(1));
-        qx = fmin(fmax(qx, T(-1)), T(1));
+    const size_t i = base + x;
+    const T xc = xb[i];
+    const T gz = (z < p.nz - 1) ? xb[i + sz] - xc : T(0);
+    const T gy = (y < p.ny - 1) ? xb[i + sy] - xc : T(0);
+    const T gx = (x < p.nx - 1) ? xb[i + 1] - xc : T(0);
+    T qz = p.R[i] + sig * gz;
+    T qy = p.R[V + i] + sig * gy;
+    T qx = p.R[2 * V + i] + sig * gx;
+    if (p.iso) {
+      const T n = sqrt(qz * qz + qy * qy + qx * qx);
+      if (n > T(1)) {
+        const T inv = T(1) / n;
+        qz *= inv; qy *= inv; qx *= inv;
       }
-      const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
-      p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
-      p.R[i] = qz + mom * (qz - oz);
-      p.R[V + i] = qy + mom * (qy - oy);
-      p.R[2 * V + i] = qx + mom * (qx - ox);
+    } else {
+      qz = fmin(fmax(qz, T(-1)), T(1));
+      qy = fmin(fmax(qy, T(-1)), T(1));
+      qx = fmin(fmax(qx, T(-1)), T(1));
     }
-  }
+    const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
+    p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
+    p.R[i] = qz + mom * (qz - oz);
+    p.R[V + i] = qy + mom * (qy - oy);
+    p.R[2 * V + i] = qx + mom * (qx - ox);
+  });
 }
 
 template <typename T>
