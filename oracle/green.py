@@ -80,6 +80,27 @@ def oversampling(N: int) -> int:
     return 4 * N if N <= 128 else 3 * N
 
 
+def kernel_lags_direct(N: int, h: float, kb: float, Q: int | None = None,
+                       workers: int | None = None) -> np.ndarray:
+    """The cropped kernel K of kernel_padded itself (lags -N..N-1 per axis in
+    wrap-around order on the 2N grid), before its forward DFT: the discrete
+    kernel of the padded convolution without the DFT round trip."""
+    import scipy.fft as sfft
+
+    Q = oversampling(N) if Q is None else Q
+    R = truncation_radius(N, h)
+    k = np.fft.fftfreq(Q, d=1.0 / Q).astype(np.int64)
+    k2 = (k[:, None, None] ** 2 + k[None, :, None] ** 2) + k[None, None, :] ** 2
+    dk = 2.0 * np.pi / (Q * h)
+    table = ghat_truncated(dk * np.sqrt(np.arange(int(k2.max()) + 1, dtype=np.float64)), kb, R)
+    gh = table[k2]
+    del k2
+    K = sfft.ifftn(gh, workers=workers, overwrite_x=True)
+    del gh
+    idx = np.r_[np.arange(0, N), np.arange(Q - N, Q)]
+    return K[np.ix_(idx, idx, idx)]
+
+
 def kernel_padded(N: int, h: float, kb: float, Q: int | None = None,
                   workers: int | None = None) -> np.ndarray:
     """ghat_P on the (2N)^3 padded grid (complex128, numpy FFT ordering).

@@ -270,3 +270,17 @@ def test_wprox_rank_r_pass_budget_is_transparent(dev):
     assert torch.equal(x1, x2) and i1.newton_total == i2.newton_total
     assert _rel(x1.cpu().numpy(), ref) < 1e-10
     px.close()
+
+
+@pytest.mark.parametrize("shape", [(3, 5, 300), (2, 3, 256), (4, 6, 128)])
+@pytest.mark.parametrize("r,tv", [(1, "iso"), (3, "aniso")])
+def test_wprox_row_lengths(dev, shape, r, tv):
+    """Rows longer than, equal to and half a workgroup (one row over several
+    steps of the threads / one row per step / two rows per step)."""
+    if r == 1:
+        v, U = _inputs(shape, 31)
+    else:
+        v, U = _inputs_rank(shape, r, 31)
+    ref = tp.wprox(v, 0.7, U, 2e-3, tv, "nonneg", n_iter=20)
+    got, info, _ = _run(dev, shape, "f64", v, 0.7, U, 2e-3, tv, "nonneg", 20)
+    assert _rel(got, ref) < 1e-10, _rel(got, ref)

@@ -126,6 +126,15 @@ def test_direct_sum_matches_fft_application():
     assert abs(K[tuple(m)] - gk) / abs(gk) < 0.05
 
 
+def test_direct_kernel_lags_equal_the_dft_round_trip():
+    """kernel_lags_direct skips the forward/inverse DFT pair of
+    kernel_lags(kernel_padded(.)): the two agree to rounding."""
+    for N in (6, 11):
+        a = green.kernel_lags(green.kernel_padded(N, H, KB))
+        b = green.kernel_lags_direct(N, H, KB)
+        assert np.max(np.abs(a - b)) / np.max(np.abs(a)) < 1e-13
+
+
 def test_oversampling_needed_for_radiating_sources():
     """A narrower Gaussian (sigma = 1.8 h) radiates appreciably at the
     background wavenumber.  With the Q = 4N oversampled kernel G matches the
