@@ -96,12 +96,73 @@ __device__ inline void dft8(C<T>* v) {
   v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
 }
 
+// cos(m pi / 8), m mod 16 (exact decimal expansions of the four distinct values)
+__host__ __device__ constexpr double cos16(int m) {
+  constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                            0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                            -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                            0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  return c[m & 15];
+}
+__host__ __device__ constexpr double sin16(int m) { return cos16(m + 12); }  // sin x = cos(x - pi/2)
+constexpr double cabs_(double x) { return x < 0 ? -x : x; }
+
+// Twiddled radix-2 butterfly (a, b) -> (a + W b, a - W b), W = W16^M (its
+// conjugate for the inverse), with W written as cos(1 + i tan) or, when
+// |tan| > 1, as sin(cot + i): 6 FMA-able operations instead of a complex
+// product and two complex sums (8); multiples of a quarter turn are adds.
+template <typename T, bool INV, int M>
+__device__ inline void tbfly(C<T>& a, C<T>& b) {
+  constexpr int m = M & 15;
+  constexpr double wr = cos16(m), wi = INV ? sin16(m) : -sin16(m);
+  C<T> wb;
+  if constexpr (m == 0) {
+    wb = b;
+  } else if constexpr (m == 8) {
+    wb = C<T>{-b.x, -b.y};
+  } else if constexpr (m == 4 || m == 12) {  // W = i wi
+    wb = wi > 0 ? C<T>{-b.y, b.x} : C<T>{b.y, -b.x};
+  } else if constexpr (cabs_(wr) >= cabs_(wi)) {
+    constexpr T t = T(wi / wr), c = T(wr);
+    const C<T> mm{b.x - t * b.y, b.y + t * b.x};
+    const C<T> y0{a.x + c * mm.x, a.y + c * mm.y}, y1{a.x - c * mm.x, a.y - c * mm.y};
+    a = y0;
+    b = y1;
+    return;
+  } else {
+    constexpr T t = T(wr / wi), c = T(wi);
+    const C<T> mm{t * b.x - b.y, t * b.y + b.x};
+    const C<T> y0{a.x + c * mm.x, a.y + c * mm.y}, y1{a.x - c * mm.x, a.y - c * mm.y};
+    a = y0;
+    b = y1;
+    return;
+  }
+  const C<T> y0 = a + wb, y1 = a - wb;
+  a = y0;
+  b = y1;
+}
+
 // 16-point DFT as 4 x 4: n = n1 + 4 n2, k = k2 + 4 k1; inner DFT-4 over n2,
-// twiddle W16^{n1 k2}, outer DFT-4 over n1; natural-order output.
+// then for each k2 the DFT-4 over n1 of a[n1][k2] W16^{n1 k2}, taken as two
+// radix-2 layers of twiddled butterflies:
+//   e+- = a0 +- W^{2k2} a2,  f+- = a1 +- W^{2k2} a3,
+//   X[k2] , X[k2+8]  = e+ +- W^{k2} f+,  X[k2+4], X[k2+12] = e- +- W^{k2+4} f-
+// (W^{k2+4} = -i W^{k2}); natural-order output.
+template <typename T, bool INV, int K2>
+__device__ inline void dft16_col(C<T> (&a)[4][4], C<T>* v) {
+  C<T> e0 = a[0][K2], e1 = a[2][K2], f0 = a[1][K2], f1 = a[3][K2];
+  tbfly<T, INV, 2 * K2>(e0, e1);
+  tbfly<T, INV, 2 * K2>(f0, f1);
+  tbfly<T, INV, K2>(e0, f0);
+  tbfly<T, INV, K2 + 4>(e1, f1);
+  v[K2] = e0;
+  v[K2 + 8] = f0;
+  v[K2 + 4] = e1;
+  v[K2 + 12] = f1;
+}
+
 template <typename T, bool INV>
 __device__ inline void dft16(C<T>* v) {
-  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173),
-          r2 = T(0.70710678118654752440);
   C<T> a[4][4];
 #pragma unroll
   for (int n1 = 0; n1 < 4; ++n1) {
@@ -109,20 +170,10 @@ __device__ inline void dft16(C<T>* v) {
     for (int n2 = 0; n2 < 4; ++n2) a[n1][n2] = v[n1 + 4 * n2];
     dft4<T, INV>(a[n1]);  // a[n1][k2]
   }
-  // W16^m = (cos(m pi/8), -sin(m pi/8)); conjugated for the inverse
-  const T sg = INV ? T(1) : T(-1);
-  const C<T> w1{c1, sg * s1}, w2{r2, sg * r2}, w3{s1, sg * c1};
-  const C<T> w6{-r2, sg * r2}, w9{-c1, -sg * s1};
-  a[1][1] = cmul(a[1][1], w1); a[1][2] = cmul(a[1][2], w2); a[1][3] = cmul(a[1][3], w3);
-  a[2][1] = cmul(a[2][1], w2); a[2][2] = rot90<T, INV>(a[2][2]); a[2][3] = cmul(a[2][3], w6);
-  a[3][1] = cmul(a[3][1], w3); a[3][2] = cmul(a[3][2], w6); a[3][3] = cmul(a[3][3], w9);
-#pragma unroll
-  for (int k2 = 0; k2 < 4; ++k2) {
-    C<T> b[4] = {a[0][k2], a[1][k2], a[2][k2], a[3][k2]};
-    dft4<T, INV>(b);
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) v[k2 + 4 * k1] = b[k1];
-  }
+  dft16_col<T, INV, 0>(a, v);
+  dft16_col<T, INV, 1>(a, v);
+  dft16_col<T, INV, 2>(a, v);
+  dft16_col<T, INV, 3>(a, v);
 }
 
 template <typename T, bool INV, int R>
