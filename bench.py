@@ -452,7 +452,8 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):
         variants[name] = {"ms_per_iter": round(float(np.mean(times)) * 1e3, 2),
                           "ms_per_iter_after_S": round(float(np.mean(later)) * 1e3, 2) if later else None,
                           "loss_first_last": [infos[0].loss, infos[-1].loss],
-                          "u_kept": sum(int(i.u_kept) for i in infos)}
+                          "u_kept": sum(int(i.u_kept) for i in infos),
+                          "metric_rank_max": max(int(i.metric_rank) for i in infos)}
         log(f"qn {name}: {iters} outer iterations, {np.mean(times) * 1e3:.1f} ms each")
     # the rank-S WPM alone (same shape, metric rank, weight and iterations)
     U = 0.1 * torch.randn((S, N, N, N), dtype=torch.float32, device=dev)

@@ -277,7 +277,9 @@ typedef struct {
   double loss;      /* F_{s'}(x_{k-1}) = (S/L) sum_{l in s'} f_l              */
   double tau;       /* tau_{s'} of Algorithm 4.2 after this iteration         */
   int u_kept;       /* 1 if s' keeps its rank-one correction                  */
-  int metric_rank;  /* columns of U passed to the WPM (0 for k <= S)          */
+  int metric_rank;  /* columns of U passed to the WPM: the subsets that hold a
+                       rank-one correction (0 for k <= S or when none does;
+                       the others are zero columns of U and are left out)   */
   double tau_sum;   /* tau of the WPM metric: alpha (k <= S) or sum_s tau_s   */
   int prox_passes;  /* root-finding passes of the WPM                        */
 } bq_qn_info;

@@ -142,6 +142,7 @@ struct bq_qn {
   void* xbar = nullptr;
   void* gbar = nullptr;
   void* U = nullptr;
+  void* Uc = nullptr;  // the kept columns of U, packed (when only some are kept)
   void* g = nullptr;
   void* v = nullptr;
   void* ybuf = nullptr;
@@ -161,7 +162,7 @@ thread_local std::string g_qn_create_error;
 
 void free_qn(bq_qn* q) {
   if (!q) return;
-  void* ptrs[] = {q->xbar, q->gbar, q->U, q->g, q->v, q->ybuf, q->ufields, q->wfields, q->part, q->res};
+  void* ptrs[] = {q->xbar, q->gbar, q->U, q->Uc, q->g, q->v, q->ybuf, q->ufields, q->wfields, q->part, q->res};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (q->hres) (void)hipHostFree(q->hres);
@@ -313,25 +314,43 @@ bq_status qn_step(bq_qn* q, void* xv, const void* y, int pick, bq_qn_info* info)
   } else {
     tau_sum = 0.0;
     for (int s = 0; s < S; ++s) tau_sum += q->tau[s];
-    rank = S;
-    hipLaunchKernelGGL((k_qn_gram<T>), dim3(q->np), dim3(QN_WG), 0, q->stream, (const T*)q->U, S, g, V, q->part);
-    if (bq_status s = qn_reduce(q, QN_K)) return s;
-    std::vector<double> M((size_t)S * S);
-    double ug[QN_RM], c[QN_RM];
-    for (int i = 0; i < S; ++i) {
-      ug[i] = q->hres[QN_NT + i];
-      for (int j = 0; j < S; ++j)
-        M[i * S + j] = (i == j ? 1.0 : 0.0) + q->hres[i <= j ? qn_tri(i, j) : qn_tri(j, i)] / tau_sum;
+    // Btilde = tau* I + U U^T: the columns of the subsets whose rank-one
+    // correction was dropped are zero, so only the kept ones enter (packed
+    // when some are missing); with none kept the metric is tau* I
+    rank = 0;
+    for (int s = 0; s < S; ++s) rank += q->kept[s] ? 1 : 0;
+    const T* Uk = (const T*)q->U;
+    if (rank > 0 && rank < S) {
+      int c = 0;
+      for (int s = 0; s < S; ++s)
+        if (q->kept[s]) {
+          if (hipMemcpyAsync((T*)q->Uc + (size_t)c * V, (const T*)q->U + (size_t)s * V, V * sizeof(T),
+                             hipMemcpyDeviceToDevice, q->stream) != hipSuccess)
+            return qn_fail(q, BQ_EDEVICE, "packing of the metric columns failed");
+          ++c;
+        }
+      Uk = (const T*)q->Uc;
     }
-    qn_chol_solve(M, S, ug, c);
-    // v = x - a S (g / tau* - U c / tau*^2)
     const double aS = p.a * S;
     QnCoef w{};
-    for (int i = 0; i < S; ++i) w.w[i] = aS * c[i] / (tau_sum * tau_sum);
-    hipLaunchKernelGGL((k_qn_v<T>), dim3(q->np), dim3(QN_WG), 0, q->stream, x, g, (const T*)q->U, S,
-                       aS / tau_sum, w, v, V);
+    if (rank > 0) {
+      hipLaunchKernelGGL((k_qn_gram<T>), dim3(q->np), dim3(QN_WG), 0, q->stream, Uk, rank, g, V, q->part);
+      if (bq_status s = qn_reduce(q, QN_K)) return s;
+      std::vector<double> M((size_t)rank * rank);
+      double ug[QN_RM], c[QN_RM];
+      for (int i = 0; i < rank; ++i) {
+        ug[i] = q->hres[QN_NT + i];
+        for (int j = 0; j < rank; ++j)
+          M[i * rank + j] = (i == j ? 1.0 : 0.0) + q->hres[i <= j ? qn_tri(i, j) : qn_tri(j, i)] / tau_sum;
+      }
+      qn_chol_solve(M, rank, ug, c);
+      for (int i = 0; i < rank; ++i) w.w[i] = aS * c[i] / (tau_sum * tau_sum);
+    }
+    // v = x - a S (g / tau* - U c / tau*^2)
+    hipLaunchKernelGGL((k_qn_v<T>), dim3(q->np), dim3(QN_WG), 0, q->stream, x, g, Uk, rank, aS / tau_sum, w, v, V);
     if (hipStreamSynchronize(q->stream) != hipSuccess) return qn_fail(q, BQ_EDEVICE, "device error");
-    sx = bq_wprox(q->px, v, tau_sum, q->U, S, aS * p.lambda, p.tv, p.cset, p.prox_iters, x, nullptr, &pst);
+    sx = bq_wprox(q->px, v, tau_sum, rank > 0 ? Uk : nullptr, rank, aS * p.lambda, p.tv, p.cset, p.prox_iters, x,
+                  nullptr, &pst);
   }
   if (sx < 0) return qn_fail(q, sx, std::string("weighted prox: ") + bq_prox_last_error(q->px));
   q->k = k;
@@ -420,7 +439,8 @@ bq_status bq_qn_create(bq_ctx* ls, bq_prox* px, const bq_qn_params* prm, const i
   q->np = (int)(g > 1024 ? 1024 : g < 1 ? 1 : g);
   const size_t img = q->V * q->es;
   if (hipMalloc(&q->xbar, p.S * img) != hipSuccess || hipMalloc(&q->gbar, p.S * img) != hipSuccess ||
-      hipMalloc(&q->U, p.S * img) != hipSuccess || hipMalloc(&q->g, img) != hipSuccess ||
+      hipMalloc(&q->U, p.S * img) != hipSuccess || hipMalloc(&q->Uc, p.S * img) != hipSuccess ||
+      hipMalloc(&q->g, img) != hipSuccess ||
       hipMalloc(&q->v, img) != hipSuccess ||
       hipMalloc(&q->ybuf, (size_t)q->maxlen * N * N * q->csz) != hipSuccess ||
       hipMalloc((void**)&q->part, (size_t)q->np * QN_K * sizeof(double)) != hipSuccess ||

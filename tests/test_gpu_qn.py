@@ -109,11 +109,14 @@ def test_qn_iteration_f64_matches_oracle(dev, tau_max, draws):
     ref = _oracle_run(tau_max, draws)
     got = _gpu_run(dev, "f64", tau_max, draws)
     kept = 0
+    state = [0] * S  # whether each subset currently holds a rank-one correction
     for k, ((xr, sp, tau, uk), (xg, info)) in enumerate(zip(ref, got), start=1):
         assert info.k == k and info.subset == sp, (k, info.subset, sp)
         assert info.u_kept == uk, k
         assert abs(info.tau - tau) <= 1e-9 * abs(tau), (k, info.tau, tau)
-        assert info.metric_rank == (0 if k <= S else S)
+        state[sp] = int(uk)
+        # only the kept corrections enter the metric (the others are zero columns)
+        assert info.metric_rank == (0 if k <= S else sum(state)), (k, info.metric_rank, state)
         err = _rel(xg, xr)
         assert err < 1e-9, (k, err)
         kept += uk
