@@ -51,7 +51,9 @@ PASS_UNITS = {
     "xy": 5.0,   # fused plane pass: read 2, write 2, transfer function 1
 }
 # Whole-call model: 28.5 V per application of G (the five passes above) and
-# about 13 V of fused vector updates per BiCGSTAB iteration.
+# 13 V of vector work per BiCGSTAB iteration: s = r - alpha v (3), the x and r
+# update (7), and the direction update p = r + beta (p - omega v) fused into
+# the first z pass (3 V beyond a plain z pass: r, p, v read, p written).
 G_UNITS = 28.5
 ITER_VEC_UNITS = 13.0
 # Non-packed FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x

@@ -240,11 +240,12 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
     const int chunk = plain ? 1 : it == 0 && hint > 0 ? hint : hint > 0 ? 1 : 4;
     it += chunk;
     for (int k = 0; k < chunk; ++k) {
-      c->timer.start(P_VEC, c->stream);
-      vec_p<T>(va, c->stream);
-      c->timer.stop(c->stream);
+      // p = r + beta (p - omega v) is formed inside the z-forward pass of A p
       a.mask = RUN_ACTIVE;
-      a.zf_mode = ZF_XV;
+      a.zf_mode = ZF_XP_UPD;
+      a.pio = va.p;
+      a.rvec = va.r;
+      a.vvec = va.v;
       a.vin = va.p;
       a.zi_mode = ZI_AV_RHAT;
       a.vz = va.p;
@@ -258,6 +259,7 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
       c->timer.stop(c->stream);
       sc_s(B, c->state, c->part_vec, c->np_vec, c->stream);
       a.mask = RUN_ACTIVE_NOT_S;
+      a.zf_mode = ZF_XV;
       a.vin = va.s;
       a.zi_mode = ZI_AS_TS;
       a.vz = va.s;

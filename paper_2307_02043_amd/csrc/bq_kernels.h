@@ -102,7 +102,6 @@ template <typename T> struct VecArgs {
   double* partial;  // B x NPV x 4
 };
 
-template <typename T> void vec_p(const VecArgs<T>& a, hipStream_t st);
 template <typename T> void vec_s(const VecArgs<T>& a, hipStream_t st);
 template <typename T> void vec_xr(const VecArgs<T>& a, hipStream_t st);
 template <typename T> void vec_norm(const VecArgs<T>& a, const C<T>* f, hipStream_t st);

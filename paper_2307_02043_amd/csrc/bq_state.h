@@ -49,6 +49,8 @@ enum ZfMode : int {
   ZF_DETCONJ = 2,  // S^T conj(r_det): conj of the detector image on z = N-1
   ZF_V = 3,        // v
   ZF_VCONJ = 4,    // conj(v)
+  ZF_XP_UPD = 5,   // BiCGSTAB direction update fused in: p = r + beta (p - omega v)
+                   // (p = r on the first iteration) written back, then x . p
 };
 
 // Epilogue of the inverse z pass.
@@ -73,6 +75,9 @@ struct PassArgs {
   const C<T>* vin;             // B x N^3
   const C<T>* rdet;            // B x N^2 detector residual
   const C<double>* inc;        // B x 3 x N plane-wave factors (x, y, z)
+  C<T>* pio;                   // ZF_XP_UPD: p (read, then overwritten)
+  const C<T>* rvec;            // ZF_XP_UPD: r
+  const C<T>* vvec;            // ZF_XP_UPD: v of the previous iteration
   // intermediates
   C<T>* zh;                    // B x 2 x N^3
   C<T>* xh;                    // B x 4 x N^3 (split xy path)

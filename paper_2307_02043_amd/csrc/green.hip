@@ -88,6 +88,30 @@ __global__ void __launch_bounds__(NT) k_zf(PassArgs<T> a) {
       for (int s = 0; s < EPT; ++s)
         if (valid(s)) orig[s] = a.vin[b * V + nof(s)];
       break;
+    case ZF_XP_UPD: {
+      const SysState& st = a.state[b];
+      const bool first = st.first;
+      const C<T> beta{(T)st.beta_x, (T)st.beta_y}, omega{(T)st.omega_x, (T)st.omega_y};
+      C<T> po[EPT], vo[EPT];
+      T xr[EPT];
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          orig[s] = a.rvec[b * V + nof(s)];
+          xr[s] = a.xpot[nof(s)];
+          if (!first) {
+            po[s] = a.pio[b * V + nof(s)];
+            vo[s] = a.vvec[b * V + nof(s)];
+          }
+        }
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          const C<T> pn = first ? orig[s] : orig[s] + cmul(beta, po[s] - cmul(omega, vo[s]));
+          a.pio[b * V + nof(s)] = pn;
+          orig[s] = pn * xr[s];
+        }
+    } break;
     default:
 #pragma unroll
       for (int s = 0; s < EPT; ++s)

@@ -73,6 +73,33 @@ __device__ __forceinline__ void zf_prologue(const PassArgs<T>& a, int b, int j, 
 #pragma unroll
       for (int m = 0; m < H; ++m) d[m] = v[(size_t)(j + R2 * m) * N2];
     } break;
+    case ZF_XP_UPD: {
+      const SysState& st = a.state[b];
+      const bool first = st.first;
+      const C<T> beta{(T)st.beta_x, (T)st.beta_y}, omega{(T)st.omega_x, (T)st.omega_y};
+      C<T>* pp = a.pio + (size_t)b * V + L;
+      const C<T>* rr = a.rvec + (size_t)b * V + L;
+      const C<T>* vv = a.vvec + (size_t)b * V + L;
+      const T* xp = a.xpot + L;
+      C<T> r[H], po[H], vo[H];
+      T xr[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const size_t o = (size_t)(j + R2 * m) * N2;
+        r[m] = rr[o];
+        xr[m] = xp[o];
+        if (!first) {
+          po[m] = pp[o];
+          vo[m] = vv[o];
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const C<T> pn = first ? r[m] : r[m] + cmul(beta, po[m] - cmul(omega, vo[m]));
+        pp[(size_t)(j + R2 * m) * N2] = pn;
+        d[m] = pn * xr[m];
+      }
+    } break;
     default: {
       const C<T>* v = a.vin + (size_t)b * V + L;
 #pragma unroll

@@ -21,28 +21,6 @@ int vec_num_partials(size_t V) {
 template <typename T>
 __device__ inline C<double> c2d(C<T> a) { return C<double>{(double)a.x, (double)a.y}; }
 
-// ---------------------------------------------------------------------------
-// p = r + beta (p - omega v)      (p = r on the first iteration)
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(VEC_WG) k_vec_p(VecArgs<T> a) {
-  const int b = blockIdx.z;
-  const SysState& s = a.state[b];
-  if (s.status != SYS_RUNNING) return;
-  const bool first = s.first;
-  const C<T> beta{(T)s.beta_x, (T)s.beta_y}, omega{(T)s.omega_x, (T)s.omega_y};
-  const size_t off = (size_t)b * a.V;
-  for (size_t i = blockIdx.x * (size_t)VEC_WG + threadIdx.x; i < a.V; i += (size_t)gridDim.x * VEC_WG) {
-    const C<T> r = a.r[off + i];
-    if (first) {
-      a.p[off + i] = r;
-    } else {
-      const C<T> d = a.p[off + i] - cmul(omega, a.v[off + i]);
-      a.p[off + i] = r + cmul(beta, d);
-    }
-  }
-}
-
 // s = r - alpha v ; partial ||s||^2
 template <typename T>
 __global__ void __launch_bounds__(VEC_WG) k_vec_s(VecArgs<T> a) {
@@ -141,10 +119,6 @@ void vec_zero_if_b0(int B, size_t V, const SysState* st, C<T>* e, hipStream_t s)
   hipLaunchKernelGGL((k_zero_if_b0<T>), dim3(vec_num_partials(V), 1, B), dim3(VEC_WG), 0, s, st, e, V);
 }
 
-template <typename T>
-void vec_p(const VecArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_vec_p<T>), dim3(vec_num_partials(a.V), 1, a.B), dim3(VEC_WG), 0, st, a);
-}
 template <typename T>
 void vec_s(const VecArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_vec_s<T>), dim3(vec_num_partials(a.V), 1, a.B), dim3(VEC_WG), 0, st, a);
@@ -459,7 +433,6 @@ void gradient(int B, int N, const C<T>* u, const C<double>* inc, const C<T>* wba
 }
 
 #define BQ_INST(T)                                                                                   \
-  template void vec_p<T>(const VecArgs<T>&, hipStream_t);                                           \
   template void vec_s<T>(const VecArgs<T>&, hipStream_t);                                           \
   template void vec_xr<T>(const VecArgs<T>&, hipStream_t);                                          \
   template void vec_norm<T>(const VecArgs<T>&, const C<T>*, hipStream_t);                           \
