@@ -70,11 +70,15 @@ struct ProxArgs {
   int iso;
 };
 
-template <typename T>
-__device__ inline T xval(const ProxArgs<T>& a, size_t i, T theta, bool nonneg, bool has_u) {
-  const T av = a.a[i];
-  const T w = has_u ? av - a.u[i] * theta : av;
-  return nonneg ? (w > T(0) ? w : T(0)) : w;
+// x = max(a - u theta, 0) (or a - u theta without the constraint, a when
+// there is no u); the two cases are compile-time, so that no load sits
+// behind a branch and the caller's loads stay in flight together.
+template <typename T, bool HAS_U, bool NONNEG>
+__device__ inline T xval(const ProxArgs<T>& a, size_t i, T theta) {
+  T w = a.a[i];
+  if constexpr (HAS_U) w = w - a.u[i] * theta;
+  if constexpr (NONNEG) w = w > T(0) ? w : T(0);
+  return w;
 }
 
 // a = v - (lambda / tau) d(R); partials: u.d, u.a, S_A(theta0), T_A(theta0).
@@ -93,16 +97,23 @@ __global__ void __launch_bounds__(PX_WG) k_div(ProxArgs<T> p) {
   const T* Rx = p.R + 2 * V;
   const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
   // (D^a)^T q at i: q[i - e_a] (if i_a > 0) - q[i] (if i_a < n_a - 1)
+  // every load is issued (at the low faces the backward neighbour is
+  // replaced by the forward one, every dimension being >= 2) and the
+  // boundary cases are selects, so that the loads of a row are in flight
+  // together instead of behind one branch-and-wait each
   auto divergence = [&](unsigned row, int x) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
     const size_t i = (size_t)row * p.nx + x;
+    const T zm = Rz[z > 0 ? i - sz : i + sz], zc = Rz[i];
+    const T ym = Ry[y > 0 ? i - sy : i + sy], yc = Ry[i];
+    const T xm = Rx[x > 0 ? i - 1 : i + 1], xc = Rx[i];
     T d = 0;
-    if (z > 0) d += Rz[i - sz];
-    if (z < p.nz - 1) d -= Rz[i];
-    if (y > 0) d += Ry[i - sy];
-    if (y < p.ny - 1) d -= Ry[i];
-    if (x > 0) d += Rx[i - 1];
-    if (x < p.nx - 1) d -= Rx[i];
+    d += z > 0 ? zm : T(0);
+    d -= z < p.nz - 1 ? zc : T(0);
+    d += y > 0 ? ym : T(0);
+    d -= y < p.ny - 1 ? yc : T(0);
+    d += x > 0 ? xm : T(0);
+    d -= x < p.nx - 1 ? xc : T(0);
     return d;
   };
   auto finish = [&](size_t i, T d, T vv, T uv) {
@@ -283,10 +294,9 @@ __global__ void __launch_bounds__(PX_WG) k_unorm(ProxArgs<T> p) {
 }
 
 // P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1})
-template <typename T>
+template <typename T, bool HAS_U, bool NONNEG>
 __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
   const ProxState* stp = p.st;
-  const bool nonneg = stp->nonneg, has_u = stp->has_u;
   const T theta = (T)stp->theta;
   const T sig = (T)p.sigma, mom = (T)stp->mom;
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
@@ -295,10 +305,16 @@ __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
     const size_t base = (size_t)row * p.nx;
     const size_t i = base + x;
-    const T xc = xval(p, i, theta, nonneg, has_u);
-    const T gz = (z < p.nz - 1) ? xval(p, i + sz, theta, nonneg, has_u) - xc : T(0);
-    const T gy = (y < p.ny - 1) ? xval(p, i + sy, theta, nonneg, has_u) - xc : T(0);
-    const T gx = (x < p.nx - 1) ? xval(p, i + 1, theta, nonneg, has_u) - xc : T(0);
+    // at the high faces the forward neighbour is replaced by the backward one
+    // (every dimension is >= 2) and discarded by the select below: all loads
+    // are issued together, none sits behind a branch
+    const T xc = xval<T, HAS_U, NONNEG>(p, i, theta);
+    const T xz = xval<T, HAS_U, NONNEG>(p, z < p.nz - 1 ? i + sz : i - sz, theta);
+    const T xy = xval<T, HAS_U, NONNEG>(p, y < p.ny - 1 ? i + sy : i - sy, theta);
+    const T xx = xval<T, HAS_U, NONNEG>(p, x < p.nx - 1 ? i + 1 : i - 1, theta);
+    const T gz = z < p.nz - 1 ? xz - xc : T(0);
+    const T gy = y < p.ny - 1 ? xy - xc : T(0);
+    const T gx = x < p.nx - 1 ? xx - xc : T(0);
     T qz = p.R[i] + sig * gz;
     T qy = p.R[V + i] + sig * gy;
     T qx = p.R[2 * V + i] + sig * gx;
@@ -321,12 +337,33 @@ __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
   });
 }
 
-template <typename T>
+template <typename T, bool HAS_U, bool NONNEG>
 __global__ void __launch_bounds__(PX_WG) k_out(ProxArgs<T> p) {
-  const bool nonneg = p.st->nonneg, has_u = p.st->has_u;
   const T theta = (T)p.st->theta;
   for (size_t i = blockIdx.x * (size_t)PX_WG + threadIdx.x; i < p.V; i += (size_t)gridDim.x * PX_WG)
-    p.x_out[i] = xval(p, i, theta, nonneg, has_u);
+    p.x_out[i] = xval<T, HAS_U, NONNEG>(p, i, theta);
+}
+
+// launch k_dual / k_out specialised on whether u exists and on the constraint
+template <typename T>
+void launch_dual(bool has_u, bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
+  if (has_u) {
+    if (nonneg) hipLaunchKernelGGL((k_dual<T, true, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_dual<T, true, false>), g, b, 0, s, a);
+  } else {
+    if (nonneg) hipLaunchKernelGGL((k_dual<T, false, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_dual<T, false, false>), g, b, 0, s, a);
+  }
+}
+template <typename T>
+void launch_out(bool has_u, bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
+  if (has_u) {
+    if (nonneg) hipLaunchKernelGGL((k_out<T, true, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_out<T, true, false>), g, b, 0, s, a);
+  } else {
+    if (nonneg) hipLaunchKernelGGL((k_out<T, false, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_out<T, false, false>), g, b, 0, s, a);
+  }
 }
 
 template <typename T>
@@ -418,7 +455,7 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       primal();
-      hipLaunchKernelGGL((k_dual<T>), g, b, 0, s, a);
+      launch_dual<T>(has_u, nonneg, g, b, s, a);
       ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
     }
     ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -437,7 +474,7 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
     return BQ_EDEVICE;
   }
   primal();
-  hipLaunchKernelGGL((k_out<T>), g, b, 0, s, a);
+  launch_out<T>(has_u, nonneg, g, b, s, a);
   if (hipGetLastError() != hipSuccess) {
     p->err = "kernel launch failed";
     return BQ_EDEVICE;

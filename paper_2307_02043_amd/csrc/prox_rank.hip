@@ -194,13 +194,18 @@ __global__ void __launch_bounds__(PR_WG) k_div_r(PRArgs<T> p) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
     const size_t base = (size_t)row * p.nx;
     const size_t i = base + x;
+    // all loads issued (at the low faces the backward neighbour is replaced
+    // by the forward one, every dimension being >= 2), boundaries as selects
+    const T zm = Rz[z > 0 ? i - sz : i + sz], zc = Rz[i];
+    const T ym = Ry[y > 0 ? i - sy : i + sy], yc = Ry[i];
+    const T xm = Rx[x > 0 ? i - 1 : i + 1], xc = Rx[i];
     T d = 0;
-    if (z > 0) d += Rz[i - sz];
-    if (z < p.nz - 1) d -= Rz[i];
-    if (y > 0) d += Ry[i - sy];
-    if (y < p.ny - 1) d -= Ry[i];
-    if (x > 0) d += Rx[i - 1];
-    if (x < p.nx - 1) d -= Rx[i];
+    d += z > 0 ? zm : T(0);
+    d -= z < p.nz - 1 ? zc : T(0);
+    d += y > 0 ? ym : T(0);
+    d -= y < p.ny - 1 ? yc : T(0);
+    d += x > 0 ? xm : T(0);
+    d -= x < p.nx - 1 ? xc : T(0);
     const T av = p.v[i] - (T)lt * d;
     p.a[i] = av;
     T u[R];
@@ -430,10 +435,14 @@ __global__ void __launch_bounds__(PR_WG) k_dual_x(PRArgs<T> p) {
     const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
     const size_t base = (size_t)row * p.nx;
     const size_t i = base + x;
+    // all loads issued (at the high faces the forward neighbour is replaced by
+    // the backward one, every dimension being >= 2), boundaries as selects
     const T xc = xb[i];
-    const T gz = (z < p.nz - 1) ? xb[i + sz] - xc : T(0);
-    const T gy = (y < p.ny - 1) ? xb[i + sy] - xc : T(0);
-    const T gx = (x < p.nx - 1) ? xb[i + 1] - xc : T(0);
+    const T xz = xb[z < p.nz - 1 ? i + sz : i - sz], xy = xb[y < p.ny - 1 ? i + sy : i - sy];
+    const T xx = xb[x < p.nx - 1 ? i + 1 : i - 1];
+    const T gz = z < p.nz - 1 ? xz - xc : T(0);
+    const T gy = y < p.ny - 1 ? xy - xc : T(0);
+    const T gx = x < p.nx - 1 ? xx - xc : T(0);
     T qz = p.R[i] + sig * gz;
     T qy = p.R[V + i] + sig * gy;
     T qx = p.R[2 * V + i] + sig * gx;
