@@ -84,22 +84,28 @@ def test_green_apply_sampled_direct_sum(dev, N, prec):
     ctx.close()
 
 
+@functools.lru_cache(maxsize=None)
+def _lags(N):
+    return green.kernel_lags_direct(N, H, KB, workers=16)
+
+
 @pytest.mark.slow
-def test_green_apply_sampled_direct_sum_256(dev):
-    """256^3 (the parity-split register passes, FP32): single outputs by
-    direct summation with the oracle's discrete kernel (its lags taken
-    without the DFT round trip)."""
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_green_apply_sampled_direct_sum_256(dev, prec):
+    """256^3 (the parity-split register passes): single outputs by direct
+    summation with the oracle's discrete kernel (its lags taken without the
+    DFT round trip)."""
     N = 256
     rng = np.random.default_rng(256)
     v = syn.random_field((1, N, N, N), rng)
-    ctx = _ctx(N, np.array([[0.0, 0.0, 1.0]]), "f32")
-    out = ctx.green(torch.from_numpy(v).to(dev, torch.complex64)).cpu().numpy()[0]
+    cd = torch.complex128 if prec == "f64" else torch.complex64
+    ctx = _ctx(N, np.array([[0.0, 0.0, 1.0]]), prec)
+    out = ctx.green(torch.from_numpy(v).to(dev, cd)).cpu().numpy()[0]
     ctx.close()
-    K = green.kernel_lags_direct(N, H, KB, workers=16)
     pts = [tuple(int(t) for t in rng.integers(0, N, 3)) for _ in range(4)] + [(0, 0, 0), (N - 1, N - 1, N - 1)]
-    ref = green.apply_G_direct(K, v[0], pts)
+    ref = green.apply_G_direct(_lags(N), v[0], pts)
     got = np.array([out[p] for p in pts])
-    assert _rel(got, ref) < 1e-5, _rel(got, ref)
+    assert _rel(got, ref) < (1e-11 if prec == "f64" else 1e-5), _rel(got, ref)
 
 
 @pytest.mark.parametrize("N,prec", [(16, "f64"), (32, "f32"), (64, "f64"), (64, "f32"), (128, "f32")])

@@ -272,11 +272,12 @@ def test_wprox_rank_r_pass_budget_is_transparent(dev):
     px.close()
 
 
-@pytest.mark.parametrize("shape", [(3, 5, 300), (2, 3, 256), (4, 6, 128)])
+@pytest.mark.parametrize("shape", [(3, 5, 300), (2, 3, 256), (4, 6, 128), (2, 2, 2), (2, 3, 2)])
 @pytest.mark.parametrize("r,tv", [(1, "iso"), (3, "aniso")])
 def test_wprox_row_lengths(dev, shape, r, tv):
     """Rows longer than, equal to and half a workgroup (one row over several
-    steps of the threads / one row per step / two rows per step)."""
+    steps of the threads / one row per step / two rows per step), and the
+    smallest images (every voxel on a face, 128 rows per step)."""
     if r == 1:
         v, U = _inputs(shape, 31)
     else:
