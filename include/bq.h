@@ -246,6 +246,14 @@ const char* bq_prox_last_error(const bq_prox* p);
  *   st     host or NULL
  * Runs on the workspace's own stream after the work pending on the stream
  * given at creation, and returns once the result is complete.
+ * Root passes: a call launches the number of root-finding passes per dual
+ * iteration that the workspace last needed plus one (at least 2); if some
+ * dual iteration needs more, the whole call is run again from the same
+ * starting point with the full pass limit, so the result never depends on
+ * the workspace's history.  With P_io given and fewer than the full passes
+ * launched, the starting dual point is first copied to a 3 x image buffer
+ * that the workspace allocates on first use (if that allocation fails, the
+ * full passes are launched instead).
  * Errors: BQ_EINVAL (arguments), BQ_EDEVICE; BQ_NOTCONV if the root-find
  * hit its pass limit in some dual iteration (x is still returned). */
 bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, double lambda, int tv,
