@@ -176,6 +176,75 @@ __device__ inline void dft16(C<T>* v) {
   dft16_col<T, INV, 3>(a, v);
 }
 
+// cos(m pi / 16), m mod 32
+__host__ __device__ constexpr double cos32(int m) {
+  constexpr double c[9] = {1.0,
+                           0.98078528040323044913,
+                           0.92387953251128675613,
+                           0.83146961230254523708,
+                           0.70710678118654752440,
+                           0.55557023301960222474,
+                           0.38268343236508977173,
+                           0.19509032201612826785,
+                           0.0};
+  const int r = m & 31;                     // angle r pi / 16 in [0, 2 pi)
+  const int q = r <= 16 ? r : 32 - r;       // cos is even about pi
+  return q <= 8 ? c[q] : -c[16 - q];        // cos(pi - t) = -cos t
+}
+__host__ __device__ constexpr double sin32(int m) { return cos32(m + 24); }  // sin x = cos(x - pi/2)
+
+// (a, b) -> (a + W b, a - W b), W = W32^M (conjugate for the inverse); same
+// tangent / cotangent forms as tbfly.
+template <typename T, bool INV, int M>
+__device__ inline void tbfly32(C<T>& a, C<T>& b) {
+  constexpr int m = M & 31;
+  if constexpr ((m & 1) == 0) {
+    tbfly<T, INV, m / 2>(a, b);  // W32^{2k} = W16^k
+  } else {
+    constexpr double wr = cos32(m), wi = INV ? sin32(m) : -sin32(m);
+    C<T> mm;
+    T c;
+    if constexpr (cabs_(wr) >= cabs_(wi)) {
+      constexpr T t = T(wi / wr);
+      c = T(wr);
+      mm = C<T>{b.x - t * b.y, b.y + t * b.x};
+    } else {
+      constexpr T t = T(wr / wi);
+      c = T(wi);
+      mm = C<T>{t * b.x - b.y, t * b.y + b.x};
+    }
+    const C<T> y0{a.x + c * mm.x, a.y + c * mm.y}, y1{a.x - c * mm.x, a.y - c * mm.y};
+    a = y0;
+    b = y1;
+  }
+}
+
+template <typename T, bool INV, int K>
+__device__ inline void dft32_join(C<T>* e, C<T>* o, C<T>* v) {
+  if constexpr (K < 16) {
+    C<T> x0 = e[K], x1 = o[K];
+    tbfly32<T, INV, K>(x0, x1);
+    v[K] = x0;
+    v[K + 16] = x1;
+    dft32_join<T, INV, K + 1>(e, o, v);
+  }
+}
+
+// 32-point DFT: radix-2 split into the even and odd samples (two DFT-16s),
+// joined by the twiddled butterflies X[k], X[k+16] = E[k] +- W32^k O[k].
+template <typename T, bool INV>
+__device__ inline void dft32(C<T>* v) {
+  C<T> e[16], o[16];
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    e[n] = v[2 * n];
+    o[n] = v[2 * n + 1];
+  }
+  dft16<T, INV>(e);
+  dft16<T, INV>(o);
+  dft32_join<T, INV, 0>(e, o, v);
+}
+
 template <typename T, bool INV, int R>
 __device__ inline void dftR(C<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v);
@@ -183,6 +252,7 @@ __device__ inline void dftR(C<T>* v) {
   else if constexpr (R == 4) dft4<T, INV>(v);
   else if constexpr (R == 8) dft8<T, INV>(v);
   else if constexpr (R == 16) dft16<T, INV>(v);
+  else if constexpr (R == 32) dft32<T, INV>(v);
   else static_assert(R == 2, "unsupported radix");
 }
 

@@ -348,7 +348,16 @@ BQ_PC(16, 8, 4)
 BQ_PC(32, 8, 8)
 BQ_PC(64, 16, 8)
 BQ_PC(128, 16, 16)
+BQ_PC(256, 32, 16)
 #undef BQ_PC
+// The padded form is used up to N = 128, and for the y pass at N = 256 in
+// complex64 (a 512-point line takes 70 KB of LDS per 16 lines; complex128
+// would need 139 KB, so it keeps the parity-split form).
+template <typename T, int N>
+struct PadSel {
+  static constexpr bool ok = PadCfg<N>::ok && (N <= 128 || sizeof(T) == 4);
+};
+
 
 // Twiddle tables of line_fft_t / line_ifft_t for the padded 2N-point lines:
 // W_{2N}^n = exp(-i pi n / N) from the half-angle table (n < 2N).
@@ -495,14 +504,20 @@ int reg_num_partials(int N) {
 
 template <typename T, int N>
 static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bool fused_xy) {
-  constexpr bool PAD = PadCfg<N>::ok;
-  constexpr int LPW = RT / (PAD ? PadCfg<N>::R2 : RegCfg<N>::R2);
+  // The y pass and the z passes choose their line form separately (same
+  // layouts): at N = 256 the padded 512-point y lines cut the y pass's
+  // vector work by ~30 %, while the z passes, bound by memory, keep the
+  // parity-split form at twice the occupancy (padded z passes measured slower).
+  constexpr bool PADY = PadSel<T, N>::ok;
+  constexpr bool PADZ = PadSel<T, N>::ok && N <= 128;
+  constexpr int LPWZ = RT / (PADZ ? PadCfg<N>::R2 : RegCfg<N>::R2);
+  constexpr int LPWY = RT / (PADY ? PadCfg<N>::R2 : RegCfg<N>::R2);
   const dim3 blk(RT);
   if (tm) tm->start(P_ZF, st);
-  if constexpr (PAD)
-    hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+  if constexpr (PADZ)
+    hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
   else
-    hipLaunchKernelGGL((k_zf_r<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+    hipLaunchKernelGGL((k_zf_r<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
   if (fused_xy) {
     if (tm) { tm->stop(st); tm->start(P_XY, st); }
     xy_fused_launch<T>(a, st);
@@ -512,18 +527,18 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
     if (tm) { tm->stop(st); tm->start(P_XF, st); }
     launch_xf_stockham<T, N>(a, st);
     if (tm) { tm->stop(st); tm->start(P_YC, st); }
-    if constexpr (PAD)  // 4 N^2 / LPW is a multiple of 8 for every padded size
-      hipLaunchKernelGGL((k_yc_p<T, N>), dim3(4 * (N * N / LPW) * a.B), blk, 0, st, a);
+    if constexpr (PADY)  // 4 N^2 / LPW is a multiple of 8 for every padded size
+      hipLaunchKernelGGL((k_yc_p<T, N>), dim3(4 * (N * N / LPWY) * a.B), blk, 0, st, a);
     else
-      hipLaunchKernelGGL((k_yc_r<T, N>), dim3(N * N / LPW, 1, 4 * a.B), blk, 0, st, a);
+      hipLaunchKernelGGL((k_yc_r<T, N>), dim3(N * N / LPWY, 1, 4 * a.B), blk, 0, st, a);
     if (tm) { tm->stop(st); tm->start(P_XI, st); }
     launch_xi_stockham<T, N>(a, st);
   }
   if (tm) { tm->stop(st); tm->start(P_ZI, st); }
-  if constexpr (PAD)
-    hipLaunchKernelGGL((k_zi_p<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+  if constexpr (PADZ)
+    hipLaunchKernelGGL((k_zi_p<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
   else
-    hipLaunchKernelGGL((k_zi_r<T, N>), dim3(N * N / LPW, 1, a.B), blk, 0, st, a);
+    hipLaunchKernelGGL((k_zi_r<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
   if (tm) tm->stop(st);
 }
 
