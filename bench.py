@@ -249,10 +249,11 @@ def main():
     csz = 8  # complex64
     alg_bytes = apps * PASS_UNITS[dom] * V * csz
     achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
-    pad = N in (16, 32, 64, 128)  # padded-line register kernels for the z and y passes
-    reg = pad or N == 256         # parity-split register kernels
-    sfx = "_p" if pad else "_r" if reg else ""
-    kname = {"yc": "k_yc" + sfx, "zf": "k_zf" + sfx, "zi": "k_zi" + sfx,
+    # register kernels: padded lines (_p) up to 128 and for the 256 y pass,
+    # parity-split lines (_r) for the 256 z passes
+    sz = "_p" if N <= 128 else "_r" if N == 256 else ""
+    sy = "_p" if N <= 256 else ""
+    kname = {"yc": "k_yc" + sy, "zf": "k_zf" + sz, "zi": "k_zi" + sz,
              "xf": "k_xf", "xi": "k_xi", "xy": "k_xy"}[dom]
     avg_ms = pass_ms[dom] / pass_n[dom]
     roofline = {"bound": "hbm", "kernel": f"{kname}<float,{N}>", "achieved": round(achieved, 1),
