@@ -156,7 +156,7 @@ def main():
                          "HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: the library runs on one GPU only; --gpus must be 1 "
               "(the gradient would shard by illuminations with one all-reduce "
               "of the N^3 gradient, which is not built here).", file=sys.stderr)
         sys.exit(2)
