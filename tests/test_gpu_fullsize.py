@@ -11,6 +11,8 @@
 * 64^3 first Born, batch of 32: gradient vs the oracle.
 * 256^3: G on a random field at sampled voxels (direct summation), and 5
   iterations of the isotropic weighted prox vs the oracle.
+* Repeated gradient calls on the same inputs are bit-identical (128^3 FP64
+  and FP32, 256^3 FP32): every reduction runs in a fixed order.
 """
 import functools
 import os
@@ -100,6 +102,27 @@ def test_128_gradient_f32_vs_f64_and_central_differences(dev):
     assert abs(fd - an) <= 1e-5 * abs(an), (fd, an)
     c64.close()
     c32.close()
+
+
+@pytest.mark.parametrize("wname,prec,B", [("c4_ls128_f32", "f64", 4), ("c4_ls128_f32", "f32", 16),
+                                          ("c5_ls256_f32", "f32", 2)])
+def test_repeated_gradient_calls_are_bit_identical(dev, wname, prec, B):
+    w = syn.WORKLOADS[wname]
+    xt = syn.scattering_potential(syn.make_phantom(w))
+    idx = syn.batch_indices(w)[:B]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    c = _ctx(w, prec, tol=1e-12 if prec == "f64" else w.tol, max_iter=w.max_iter)
+    y = c.forward(torch.from_numpy(xt).to(dev).to(dt), idx)[0]
+    x = torch.from_numpy(0.5 * xt).to(dev).to(dt)
+    g1, f1, i1 = c.grad(x, y, idx, 1.0 / B)
+    g1 = g1.clone()
+    f0, _ = c.loss(x, y, idx, 1.0 / B)
+    g2, f2, i2 = c.grad(x, y, idx, 1.0 / B)
+    assert i1.status == 0 and i2.status == 0
+    assert f1 == f2 == f0
+    assert list(i1.iters_fwd) == list(i2.iters_fwd) and list(i1.iters_adj) == list(i2.iters_adj)
+    assert torch.equal(g1, g2)
+    c.close()
 
 
 def test_96_radix3_gradient_matches_oracle(dev):
