@@ -518,6 +518,25 @@ __device__ inline void for_rows(int nx, unsigned nrows, F&& f) {
 }
 
 // ---------------------------------------------------------------------------
+// Streaming element access (non-temporal hint), for values that are read or
+// written once per kernel and not reused from the caches.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline C<T> sld(const C<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return C<T>{v.x, v.y};
+}
+template <typename T>
+__device__ inline void sst(C<T>* p, C<T> c) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = c.x;
+  v.y = c.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+
+// ---------------------------------------------------------------------------
 // Raw buffer access: a resource per workgroup-uniform slice, a per-thread
 // byte offset and a compile-time (scalar) byte offset per access, so that a
 // strided sweep costs no vector address arithmetic.  Word 3 of the resource
@@ -528,22 +547,25 @@ using brsrc = __amdgpu_buffer_rsrc_t;
 __device__ inline brsrc make_rsrc(const void* base, size_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(uint32_t)bytes, 0x00020000);
 }
-template <typename T>
+// STREAM: non-temporal hint (cache-policy bit nt) for single-use data
+template <typename T, bool STREAM = false>
 __device__ inline C<T> bload(brsrc r, uint32_t voff, uint32_t soff) {
+  constexpr int aux = STREAM ? 2 : 0;
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, aux));
   } else {
-    return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, aux));
   }
 }
-template <typename T>
+template <typename T, bool STREAM = false>
 __device__ inline void bstore(C<T> v, brsrc r, uint32_t voff, uint32_t soff) {
+  constexpr int aux = STREAM ? 2 : 0;
   if constexpr (sizeof(T) == 4) {
     using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, aux);
   } else {
     using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, voff, soff, aux);
   }
 }
 

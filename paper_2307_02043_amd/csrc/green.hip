@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(NT) k_xf(PassArgs<T> a) {
 #pragma unroll
   for (int s = 0; s < EPT; ++s) {
     const int e = tid + s * NT;
-    if ((TOT % NT) == 0 || e < TOT) orig[s] = src[e];
+    if ((TOT % NT) == 0 || e < TOT) orig[s] = sld(&src[e]);
   }
   const int pz = row0 / (int)N2;  // TL divides N, so a tile never straddles pz
   const size_t rest0 = (size_t)row0 - (size_t)pz * N2;
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(NT) k_xf(PassArgs<T> a) {
       const int e = tid + s * NT;
       if ((TOT % NT) == 0 || e < TOT) {
         const int rl = e / N, x = e - rl * N;
-        dst[e] = lds[rl * LS + x];
+        sst(&dst[e], lds[rl * LS + x]);
       }
     }
     __syncthreads();
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(NT) k_xi(PassArgs<T> a) {
       const int e = tid + s * NT;
       if ((TOT % NT) == 0 || e < TOT) {
         const int rl = e / N, x = e - rl * N;
-        lds[rl * LS + x] = src[e];
+        lds[rl * LS + x] = sld(&src[e]);
       }
     }
     __syncthreads();
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(NT) k_xi(PassArgs<T> a) {
 #pragma unroll
   for (int s = 0; s < EPT; ++s) {
     const int e = tid + s * NT;
-    if ((TOT % NT) == 0 || e < TOT) dst[e] = acc[s];
+    if ((TOT % NT) == 0 || e < TOT) sst(&dst[e], acc[s]);
   }
 }
 

@@ -46,7 +46,7 @@ __device__ __forceinline__ void zf_prologue(const PassArgs<T>& a, int b, int j, 
       T xr[H];
 #pragma unroll
       for (int m = 0; m < H; ++m) {
-        d[m] = v[(size_t)(j + R2 * m) * N2];
+        d[m] = sld(&v[(size_t)(j + R2 * m) * N2]);
         xr[m] = xp[(size_t)(j + R2 * m) * N2];
       }
 #pragma unroll
@@ -71,7 +71,7 @@ __device__ __forceinline__ void zf_prologue(const PassArgs<T>& a, int b, int j, 
     case ZF_V: {
       const C<T>* v = a.vin + (size_t)b * V + L;
 #pragma unroll
-      for (int m = 0; m < H; ++m) d[m] = v[(size_t)(j + R2 * m) * N2];
+      for (int m = 0; m < H; ++m) d[m] = sld(&v[(size_t)(j + R2 * m) * N2]);
     } break;
     case ZF_XP_UPD: {
       const SysState& st = a.state[b];
@@ -86,24 +86,24 @@ __device__ __forceinline__ void zf_prologue(const PassArgs<T>& a, int b, int j, 
 #pragma unroll
       for (int m = 0; m < H; ++m) {
         const size_t o = (size_t)(j + R2 * m) * N2;
-        r[m] = rr[o];
+        r[m] = sld(&rr[o]);
         xr[m] = xp[o];
         if (!first) {
-          po[m] = pp[o];
-          vo[m] = vv[o];
+          po[m] = sld(&pp[o]);
+          vo[m] = sld(&vv[o]);
         }
       }
 #pragma unroll
       for (int m = 0; m < H; ++m) {
         const C<T> pn = first ? r[m] : r[m] + cmul(beta, po[m] - cmul(omega, vo[m]));
-        pp[(size_t)(j + R2 * m) * N2] = pn;
+        sst(&pp[(size_t)(j + R2 * m) * N2], pn);
         d[m] = pn * xr[m];
       }
     } break;
     default: {
       const C<T>* v = a.vin + (size_t)b * V + L;
 #pragma unroll
-      for (int m = 0; m < H; ++m) d[m] = conj(v[(size_t)(j + R2 * m) * N2]);
+      for (int m = 0; m < H; ++m) d[m] = conj(sld(&v[(size_t)(j + R2 * m) * N2]));
     } break;
   }
 }
@@ -120,11 +120,11 @@ __device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, 
   switch (a.zi_mode) {
     case ZI_G:
 #pragma unroll
-      for (int m = 0; m < H; ++m) out[(size_t)(j + R2 * m) * N2] = gw[m];
+      for (int m = 0; m < H; ++m) sst(&out[(size_t)(j + R2 * m) * N2], gw[m]);
       break;
     case ZI_GCONJ:
 #pragma unroll
-      for (int m = 0; m < H; ++m) out[(size_t)(j + R2 * m) * N2] = conj(gw[m]);
+      for (int m = 0; m < H; ++m) sst(&out[(size_t)(j + R2 * m) * N2], conj(gw[m]));
       break;
     case ZI_AV_RHAT: {
       const C<T>* vz = a.vz + (size_t)b * V + L;
@@ -132,13 +132,13 @@ __device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, 
       C<T> o[H], rh[H];
 #pragma unroll
       for (int m = 0; m < H; ++m) {
-        o[m] = vz[(size_t)(j + R2 * m) * N2];
-        rh[m] = rhat[(size_t)(j + R2 * m) * N2];
+        o[m] = sld(&vz[(size_t)(j + R2 * m) * N2]);
+        rh[m] = sld(&rhat[(size_t)(j + R2 * m) * N2]);
       }
 #pragma unroll
       for (int m = 0; m < H; ++m) {
         o[m] = o[m] - gw[m];
-        out[(size_t)(j + R2 * m) * N2] = o[m];
+        sst(&out[(size_t)(j + R2 * m) * N2], o[m]);
         red[0] += (double)rh[m].x * o[m].x + (double)rh[m].y * o[m].y;
         red[1] += (double)rh[m].x * o[m].y - (double)rh[m].y * o[m].x;
       }
@@ -147,11 +147,11 @@ __device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, 
       const C<T>* vz = a.vz + (size_t)b * V + L;
       C<T> sv[H];
 #pragma unroll
-      for (int m = 0; m < H; ++m) sv[m] = vz[(size_t)(j + R2 * m) * N2];
+      for (int m = 0; m < H; ++m) sv[m] = sld(&vz[(size_t)(j + R2 * m) * N2]);
 #pragma unroll
       for (int m = 0; m < H; ++m) {
         const C<T> o = sv[m] - gw[m];
-        out[(size_t)(j + R2 * m) * N2] = o;
+        sst(&out[(size_t)(j + R2 * m) * N2], o);
         red[0] += (double)o.x * sv[m].x + (double)o.y * sv[m].y;
         red[1] += (double)o.x * sv[m].y - (double)o.y * sv[m].x;
         red[2] += (double)o.x * o.x + (double)o.y * o.y;
@@ -163,21 +163,21 @@ __device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, 
       if (a.bsrc) {
         const C<T>* bs = a.bsrc + (size_t)b * V + L;
 #pragma unroll
-        for (int m = 0; m < H; ++m) o[m] = bs[(size_t)(j + R2 * m) * N2] - e0[(size_t)(j + R2 * m) * N2];
+        for (int m = 0; m < H; ++m) o[m] = sld(&bs[(size_t)(j + R2 * m) * N2]) - sld(&e0[(size_t)(j + R2 * m) * N2]);
       } else {
         const int y = L / N, x = L - y * N;
         const C<double>* t = a.inc + (size_t)b * 3 * N;
         const C<double> txy = cmul(t[x], t[N + y]);
 #pragma unroll
         for (int m = 0; m < H; ++m)
-          o[m] = cvt_r<T>(cmul(txy, t[2 * N + j + R2 * m])) - e0[(size_t)(j + R2 * m) * N2];
+          o[m] = cvt_r<T>(cmul(txy, t[2 * N + j + R2 * m])) - sld(&e0[(size_t)(j + R2 * m) * N2]);
       }
       C<T>* out2 = a.out2 + (size_t)b * V + L;
 #pragma unroll
       for (int m = 0; m < H; ++m) {
         o[m] = o[m] + gw[m];
-        out[(size_t)(j + R2 * m) * N2] = o[m];
-        out2[(size_t)(j + R2 * m) * N2] = o[m];
+        sst(&out[(size_t)(j + R2 * m) * N2], o[m]);
+        sst(&out2[(size_t)(j + R2 * m) * N2], o[m]);
         red[2] += (double)o[m].x * o[m].x + (double)o[m].y * o[m].y;
       }
     } break;
@@ -185,8 +185,8 @@ __device__ __forceinline__ void zi_epilogue(const PassArgs<T>& a, int b, int j, 
       C<T>* out2 = a.out2 ? a.out2 + (size_t)b * V + L : nullptr;
 #pragma unroll
       for (int m = 0; m < H; ++m) {
-        out[(size_t)(j + R2 * m) * N2] = gw[m];
-        if (out2) out2[(size_t)(j + R2 * m) * N2] = gw[m];
+        sst(&out[(size_t)(j + R2 * m) * N2], gw[m]);
+        if (out2) sst(&out2[(size_t)(j + R2 * m) * N2], gw[m]);
         red[2] += (double)gw[m].x * gw[m].x + (double)gw[m].y * gw[m].y;
       }
     } break;
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(RT) k_zf_r(PassArgs<T> a) {
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
         const int kz = (j + R2 * i) + R1 * k2;
-        dst[(size_t)kz * N2] = d[i * R2 + k2];
+        sst(&dst[(size_t)kz * N2], d[i * R2 + k2]);
       }
   }
 }
@@ -257,7 +257,7 @@ __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
   C<T> orig[R1], acc[R1], d[R1];
 #pragma unroll
   for (int m = 0; m < R1; ++m) {
-    orig[m] = col[(size_t)(j + R2 * m) * N];
+    orig[m] = sld(&col[(size_t)(j + R2 * m) * N]);
     acc[m] = C<T>{0, 0};
   }
   __syncthreads();
@@ -278,7 +278,7 @@ __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
     for (int m = 0; m < R1; ++m) acc[m] = acc[m] + (py ? cmulc(d[m], th[j + R2 * m]) : d[m]);
   }
 #pragma unroll
-  for (int m = 0; m < R1; ++m) col[(size_t)(j + R2 * m) * N] = acc[m];
+  for (int m = 0; m < R1; ++m) sst(&col[(size_t)(j + R2 * m) * N], acc[m]);
 }
 
 // z lines, inverse, both z parities summed, epilogue and FP64 partials.
@@ -305,7 +305,7 @@ __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) d[i * R2 + k2] = src[(size_t)((j + R2 * i) + R1 * k2) * N2];
+      for (int k2 = 0; k2 < R2; ++k2) d[i * R2 + k2] = sld(&src[(size_t)((j + R2 * i) + R1 * k2) * N2]);
     line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
 #pragma unroll
     for (int m = 0; m < R1; ++m) acc[m] = acc[m] + (pz ? cmulc(d[m], th[j + R2 * m]) : d[m]);
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(RT) k_zf_p(PassArgs<T> a) {
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
-      bstore<T>(d[i * R2 + k2], rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
+      bstore<T, true>(d[i * R2 + k2], rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
 }
 
 // y columns of class (pz, px), line L = kz N + kx
@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   const uint32_t vo = (uint32_t)(kz * N * N + kx + j * N) * SZ;
   C<T> d[R1];
 #pragma unroll
-  for (int m = 0; m < R1; ++m) d[m] = (m < H) ? bload<T>(rc, vo, (uint32_t)(m * R2 * N) * SZ) : C<T>{0, 0};
+  for (int m = 0; m < R1; ++m) d[m] = (m < H) ? bload<T, true>(rc, vo, (uint32_t)(m * R2 * N) * SZ) : C<T>{0, 0};
   // padded frequency kp = k1 + R1 k2 (k1 = j + R2 i) is py class kp & 1 = j & 1
   // at index kp >> 1; classes (pz, 0, px) and (pz, 1, px) are 2V apart
   const brsrc rg = make_rsrc(a.ghat + (size_t)(pz * 4 + px) * V, 3 * V * SZ);
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
       d[i * R2 + k2] = cmul(d[i * R2 + k2], bload<T>(rg, vg, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N) * SZ));
   line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
 #pragma unroll
-  for (int m = 0; m < H; ++m) bstore<T>(d[m], rc, vo, (uint32_t)(m * R2 * N) * SZ);
+  for (int m = 0; m < H; ++m) bstore<T, true>(d[m], rc, vo, (uint32_t)(m * R2 * N) * SZ);
 }
 
 // z lines, inverse (first N outputs of the padded inverse), epilogue
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(RT) k_zi_p(PassArgs<T> a) {
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
-      d[i * R2 + k2] = bload<T>(rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
+      d[i * R2 + k2] = bload<T, true>(rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
   __syncthreads();
   line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
   double red[3] = {0.0, 0.0, 0.0};

@@ -32,8 +32,8 @@ __global__ void __launch_bounds__(VEC_WG) k_vec_s(VecArgs<T> a) {
   const size_t off = (size_t)b * a.V;
   double acc[1] = {0.0};
   for (size_t i = blockIdx.x * (size_t)VEC_WG + threadIdx.x; i < a.V; i += (size_t)gridDim.x * VEC_WG) {
-    const C<T> sv = a.r[off + i] - cmul(alpha, a.v[off + i]);
-    a.s[off + i] = sv;
+    const C<T> sv = sld(&a.r[off + i]) - cmul(alpha, sld(&a.v[off + i]));
+    sst(&a.s[off + i], sv);
     acc[0] += (double)sv.x * sv.x + (double)sv.y * sv.y;
   }
   block_sum<VEC_WG, 1>(acc, scratch);
@@ -57,13 +57,13 @@ __global__ void __launch_bounds__(VEC_WG) k_vec_xr(VecArgs<T> a) {
   for (size_t i = blockIdx.x * (size_t)VEC_WG + threadIdx.x; i < a.V; i += (size_t)gridDim.x * VEC_WG) {
     const size_t k = off + i;
     if (half) {
-      a.e[k] = a.e[k] + cmul(alpha, a.p[k]);
+      sst(&a.e[k], sld(&a.e[k]) + cmul(alpha, sld(&a.p[k])));
     } else {
-      const C<T> sv = a.s[k];
-      a.e[k] = a.e[k] + cmul(alpha, a.p[k]) + cmul(omega, sv);
-      const C<T> r = sv - cmul(omega, a.t[k]);
-      a.r[k] = r;
-      const C<T> rh = a.rhat[k];
+      const C<T> sv = sld(&a.s[k]);
+      sst(&a.e[k], sld(&a.e[k]) + cmul(alpha, sld(&a.p[k])) + cmul(omega, sv));
+      const C<T> r = sv - cmul(omega, sld(&a.t[k]));
+      sst(&a.r[k], r);
+      const C<T> rh = sld(&a.rhat[k]);
       acc[0] += (double)r.x * r.x + (double)r.y * r.y;
       acc[1] += (double)rh.x * r.x + (double)rh.y * r.y;
       acc[2] += (double)rh.x * r.y - (double)rh.y * r.x;
