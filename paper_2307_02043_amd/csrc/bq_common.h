@@ -522,6 +522,10 @@ __device__ inline void for_rows(int nx, unsigned nrows, F&& f) {
 // written once per kernel and not reused from the caches.
 // ---------------------------------------------------------------------------
 template <typename T>
+__device__ inline T nt_ld(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ inline void nt_st(T* p, T v) { __builtin_nontemporal_store(v, p); }
+template <typename T>
 __device__ inline C<T> sld(const C<T>* p) {
   typedef T v2 __attribute__((ext_vector_type(2)));
   const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));

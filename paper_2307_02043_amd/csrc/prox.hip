@@ -34,6 +34,7 @@ namespace bq {
 
 constexpr int PX_WG = 256;
 
+
 struct ProxState {
   double tau, lam;
   double unorm2, M;
@@ -131,11 +132,11 @@ __global__ void __launch_bounds__(PX_WG) k_div(ProxArgs<T> p) {
   for_row_pairs<PX_WG>(p.nx, nrows, [&](unsigned row0, unsigned row1, bool two, int x) {
     const size_t i0 = (size_t)row0 * p.nx + x, i1 = (size_t)row1 * p.nx + x;
     const T d0 = divergence(row0, x);
-    const T v0 = p.v[i0], u0 = s.has_u ? p.u[i0] : T(0);
+    const T v0 = nt_ld(&p.v[i0]), u0 = s.has_u ? p.u[i0] : T(0);
     T d1 = 0, v1 = 0, u1 = 0;
     if (two) {
       d1 = divergence(row1, x);
-      v1 = p.v[i1];
+      v1 = nt_ld(&p.v[i1]);
       u1 = s.has_u ? p.u[i1] : T(0);
     }
     finish(i0, d0, v0, u0);
@@ -293,7 +294,9 @@ __global__ void __launch_bounds__(PX_WG) k_unorm(ProxArgs<T> p) {
   if (threadIdx.x == 0) p.partial[(size_t)blockIdx.x * 4] = acc[0];
 }
 
-// P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1})
+// P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1}).
+// R and P are read and written once per voxel (non-temporal); a and u are
+// re-read as stencil neighbours and keep the default cache policy.
 template <typename T, bool HAS_U, bool NONNEG>
 __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
   const ProxState* stp = p.st;
@@ -315,9 +318,9 @@ __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
     const T gz = z < p.nz - 1 ? xz - xc : T(0);
     const T gy = y < p.ny - 1 ? xy - xc : T(0);
     const T gx = x < p.nx - 1 ? xx - xc : T(0);
-    T qz = p.R[i] + sig * gz;
-    T qy = p.R[V + i] + sig * gy;
-    T qx = p.R[2 * V + i] + sig * gx;
+    T qz = nt_ld(&p.R[i]) + sig * gz;
+    T qy = nt_ld(&p.R[V + i]) + sig * gy;
+    T qx = nt_ld(&p.R[2 * V + i]) + sig * gx;
     if (p.iso) {
       const T n = sqrt(qz * qz + qy * qy + qx * qx);
       if (n > T(1)) {
@@ -329,11 +332,11 @@ __global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
       qy = fmin(fmax(qy, T(-1)), T(1));
       qx = fmin(fmax(qx, T(-1)), T(1));
     }
-    const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
-    p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
-    p.R[i] = qz + mom * (qz - oz);
-    p.R[V + i] = qy + mom * (qy - oy);
-    p.R[2 * V + i] = qx + mom * (qx - ox);
+    const T oz = nt_ld(&p.P[i]), oy = nt_ld(&p.P[V + i]), ox = nt_ld(&p.P[2 * V + i]);
+    nt_st(&p.P[i], qz); nt_st(&p.P[V + i], qy); nt_st(&p.P[2 * V + i], qx);
+    nt_st(&p.R[i], qz + mom * (qz - oz));
+    nt_st(&p.R[V + i], qy + mom * (qy - oy));
+    nt_st(&p.R[2 * V + i], qx + mom * (qx - ox));
   });
 }
 

@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(PR_WG) k_div_r(PRArgs<T> p) {
     d -= y < p.ny - 1 ? yc : T(0);
     d += x > 0 ? xm : T(0);
     d -= x < p.nx - 1 ? xc : T(0);
-    const T av = p.v[i] - (T)lt * d;
+    const T av = nt_ld(&p.v[i]) - (T)lt * d;
     p.a[i] = av;
     T u[R];
 #pragma unroll
@@ -424,7 +424,8 @@ __global__ void __launch_bounds__(PR_WG) k_xr(PRArgs<T> p, T* out) {
   }
 }
 
-// P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1})
+// P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1}).
+// R and P are streamed (non-temporal); x is re-read by the stencil.
 template <typename T>
 __global__ void __launch_bounds__(PR_WG) k_dual_x(PRArgs<T> p) {
   const T sig = (T)p.sigma, mom = (T)p.st->mom;
@@ -443,9 +444,9 @@ __global__ void __launch_bounds__(PR_WG) k_dual_x(PRArgs<T> p) {
     const T gz = z < p.nz - 1 ? xz - xc : T(0);
     const T gy = y < p.ny - 1 ? xy - xc : T(0);
     const T gx = x < p.nx - 1 ? xx - xc : T(0);
-    T qz = p.R[i] + sig * gz;
-    T qy = p.R[V + i] + sig * gy;
-    T qx = p.R[2 * V + i] + sig * gx;
+    T qz = nt_ld(&p.R[i]) + sig * gz;
+    T qy = nt_ld(&p.R[V + i]) + sig * gy;
+    T qx = nt_ld(&p.R[2 * V + i]) + sig * gx;
     if (p.iso) {
       const T n = sqrt(qz * qz + qy * qy + qx * qx);
       if (n > T(1)) {
@@ -457,11 +458,11 @@ __global__ void __launch_bounds__(PR_WG) k_dual_x(PRArgs<T> p) {
       qy = fmin(fmax(qy, T(-1)), T(1));
       qx = fmin(fmax(qx, T(-1)), T(1));
     }
-    const T oz = p.P[i], oy = p.P[V + i], ox = p.P[2 * V + i];
-    p.P[i] = qz; p.P[V + i] = qy; p.P[2 * V + i] = qx;
-    p.R[i] = qz + mom * (qz - oz);
-    p.R[V + i] = qy + mom * (qy - oy);
-    p.R[2 * V + i] = qx + mom * (qx - ox);
+    const T oz = nt_ld(&p.P[i]), oy = nt_ld(&p.P[V + i]), ox = nt_ld(&p.P[2 * V + i]);
+    nt_st(&p.P[i], qz); nt_st(&p.P[V + i], qy); nt_st(&p.P[2 * V + i], qx);
+    nt_st(&p.R[i], qz + mom * (qz - oz));
+    nt_st(&p.R[V + i], qy + mom * (qy - oy));
+    nt_st(&p.R[2 * V + i], qx + mom * (qx - ox));
   });
 }
 
