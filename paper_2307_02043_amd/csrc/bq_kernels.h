@@ -76,6 +76,7 @@ template <typename T> bool reg_supported(int N);
 template <typename T, int N> void launch_xf_stockham(const PassArgs<T>& a, hipStream_t st);
 template <typename T, int N> void launch_xi_stockham(const PassArgs<T>& a, hipStream_t st);
 template <typename T> int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm);
+template <typename T>
 int reg_num_partials(int N);
 template <typename T> int xy_fused_launch(const PassArgs<T>& a, hipStream_t st);
 template <typename T> int ghat_precompute(int N, double h, double kb, C<T>* out, hipStream_t st);

@@ -466,7 +466,7 @@ static void launch_split_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) 
 
 template <typename T>
 int green_num_partials(int N) {
-  if (reg_supported<T>(N)) return reg_num_partials(N);
+  if (reg_supported<T>(N)) return reg_num_partials<T>(N);
   switch (N) {
 #define BQ_NP(n) case n: return (n / tile_w<T>(n)) * n;
     BQ_NP(8) BQ_NP(12) BQ_NP(16) BQ_NP(24) BQ_NP(32) BQ_NP(48) BQ_NP(64) BQ_NP(96) BQ_NP(128) BQ_NP(256)

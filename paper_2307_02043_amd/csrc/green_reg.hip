@@ -361,9 +361,9 @@ struct PadSel {
 
 // Twiddle tables of line_fft_t / line_ifft_t for the padded 2N-point lines:
 // W_{2N}^n = exp(-i pi n / N) from the half-angle table (n < 2N).
-template <typename T, int N, int R1, int R2>
+template <typename T, int N, int R1, int R2, int NTH = RT>
 __device__ inline void load_twtab_pad(C<T>* t, const C<T>* twH, int tid) {
-  for (int e = tid; e < R1 * R2; e += RT) {
+  for (int e = tid; e < R1 * R2; e += NTH) {
     const int a = e / R1, b = e - a * R1, n = a * b;
     const C<T> w = twH[n < N ? n : n - N];
     const C<T> v = n < N ? w : C<T>{-w.x, -w.y};
@@ -372,16 +372,25 @@ __device__ inline void load_twtab_pad(C<T>* t, const C<T>* twH, int tid) {
   }
 }
 
+// Threads per workgroup of the padded z passes: 64 lines of complex64 at
+// N = 128, so that one wave instruction covers 512 contiguous bytes of a
+// z plane instead of four 128-byte pieces (16 lines elsewhere; complex128
+// would not fit in LDS).  The y pass keeps 16 lines: its 16-wave barrier
+// would stall a pass bound by vector issue.
 template <typename T, int N>
-__global__ void __launch_bounds__(RT) k_zf_p(PassArgs<T> a) {
-  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, NI = R1 / R2;
+constexpr int rtz() { return (N == 128 && sizeof(T) == 4) ? 1024 : RT; }
+
+template <typename T, int N>
+__global__ void __launch_bounds__((rtz<T, N>())) k_zf_p(PassArgs<T> a) {
+  constexpr int NTH = rtz<T, N>();
+  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = NTH / R2, NI = R1 / R2;
   constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;  // H: nonzero inputs per thread
   constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
   __shared__ C<T> twt[LineX<R1, R2>::TW];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_twtab_pad<T, N, R1, R2>(twt, a.twH, tid);
+  load_twtab_pad<T, N, R1, R2, NTH>(twt, a.twH, tid);
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
   C<T> d[R1];
@@ -447,16 +456,17 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
 
 // z lines, inverse (first N outputs of the padded inverse), epilogue
 template <typename T, int N>
-__global__ void __launch_bounds__(RT) k_zi_p(PassArgs<T> a) {
-  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, NI = R1 / R2;
+__global__ void __launch_bounds__((rtz<T, N>())) k_zi_p(PassArgs<T> a) {
+  constexpr int NTH = rtz<T, N>();
+  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = NTH / R2, NI = R1 / R2;
   constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;
   constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
   __shared__ C<T> twt[LineX<R1, R2>::TW];
-  __shared__ double red_scratch[(RT / 64) * 3];
+  __shared__ double red_scratch[(NTH / 64) * 3];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_twtab_pad<T, N, R1, R2>(twt, a.twH, tid);
+  load_twtab_pad<T, N, R1, R2, NTH>(twt, a.twH, tid);
   const int L = blockIdx.x * LPW + line;
   const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * N * N * N, 2 * (size_t)N * N * N * SZ);
   const uint32_t vo = (uint32_t)((j & 1) * N * N * N + (j >> 1) * N * N + L) * SZ;
@@ -472,7 +482,7 @@ __global__ void __launch_bounds__(RT) k_zi_p(PassArgs<T> a) {
   const int mode = a.zi_mode;
   zi_epilogue<T, N, R2, H>(a, b, j, L, d, red);
   if (mode >= ZI_AV_RHAT) {
-    block_sum<RT, 3>(red, red_scratch);
+    block_sum<NTH, 3>(red, red_scratch);
     if (tid == 0) {
       double* p = a.partial + ((size_t)b * gridDim.x + blockIdx.x) * 4;
       p[0] = red[0];
@@ -491,12 +501,13 @@ bool reg_supported(int N) {
   }
 }
 
+template <typename T>
 int reg_num_partials(int N) {
   switch (N) {  // grid of the z-inverse kernel (padded variant up to 128)
-    case 16: return N * N / (RT / PadCfg<16>::R2);
-    case 32: return N * N / (RT / PadCfg<32>::R2);
-    case 64: return N * N / (RT / PadCfg<64>::R2);
-    case 128: return N * N / (RT / PadCfg<128>::R2);
+    case 16: return N * N / (rtz<T, 16>() / PadCfg<16>::R2);
+    case 32: return N * N / (rtz<T, 32>() / PadCfg<32>::R2);
+    case 64: return N * N / (rtz<T, 64>() / PadCfg<64>::R2);
+    case 128: return N * N / (rtz<T, 128>() / PadCfg<128>::R2);
     case 256: return N * N / (RT / RegCfg<256>::R2);
     default: return -1;
   }
@@ -510,12 +521,13 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
   // parity-split form at twice the occupancy (padded z passes measured slower).
   constexpr bool PADY = PadSel<T, N>::ok;
   constexpr bool PADZ = PadSel<T, N>::ok && N <= 128;
-  constexpr int LPWZ = RT / (PADZ ? PadCfg<N>::R2 : RegCfg<N>::R2);
+  constexpr int NTZ = PADZ ? rtz<T, N>() : RT;  // threads of the z kernels
+  constexpr int LPWZ = NTZ / (PADZ ? PadCfg<N>::R2 : RegCfg<N>::R2);
   constexpr int LPWY = RT / (PADY ? PadCfg<N>::R2 : RegCfg<N>::R2);
   const dim3 blk(RT);
   if (tm) tm->start(P_ZF, st);
   if constexpr (PADZ)
-    hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
+    hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPWZ, 1, a.B), dim3(NTZ), 0, st, a);
   else
     hipLaunchKernelGGL((k_zf_r<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
   if (fused_xy) {
@@ -536,7 +548,7 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
   }
   if (tm) { tm->stop(st); tm->start(P_ZI, st); }
   if constexpr (PADZ)
-    hipLaunchKernelGGL((k_zi_p<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
+    hipLaunchKernelGGL((k_zi_p<T, N>), dim3(N * N / LPWZ, 1, a.B), dim3(NTZ), 0, st, a);
   else
     hipLaunchKernelGGL((k_zi_r<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
   if (tm) tm->stop(st);
@@ -558,6 +570,8 @@ int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
 
 template bool reg_supported<float>(int);
 template bool reg_supported<double>(int);
+template int reg_num_partials<float>(int);
+template int reg_num_partials<double>(int);
 template int reg_apply<float>(const PassArgs<float>&, hipStream_t, PassTimer*);
 template int reg_apply<double>(const PassArgs<double>&, hipStream_t, PassTimer*);
 
