@@ -58,3 +58,24 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.bq_create(ctypes.byref(g), bad, 1, None, ctypes.byref(out)) == L.BQ_EINVAL
     assert lib.bq_create(ctypes.byref(g), d, 0, None, ctypes.byref(out)) == L.BQ_EINVAL
     assert lib.bq_destroy(None) == L.BQ_OK
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: without the built library the binding raises."""
+    import pytest
+    from paper_2307_02043_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libbq.so"))
+    with pytest.raises(ImportError, match="is missing"):
+        _lib.load()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus N > 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
