@@ -66,6 +66,11 @@ typedef enum { BQ_MODEL_LS = 0, BQ_MODEL_BORN = 1 } bq_model;
 #define BQ_FLAG_FUSED_XY 2u /* run the x/y FFTs of G as one LDS-resident plane
                                pass where it exists (N = 16..128 complex64,
                                16..64 complex128) instead of three passes   */
+#define BQ_FLAG_GRAPH 4u    /* batched solves replay one captured BiCGSTAB
+                               iteration as a HIP graph on a stream of the
+                               library's own instead of launching its kernels
+                               one by one (same results; measured no faster
+                               for these kernel lengths, so not the default) */
 
 /* Grid, optics and solver settings (Section 6.1 describes the setting). */
 typedef struct {

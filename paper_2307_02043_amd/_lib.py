@@ -17,6 +17,7 @@ BQ_F32, BQ_F64 = 0, 1
 BQ_MODEL_LS, BQ_MODEL_BORN = 0, 1
 BQ_FLAG_PLAIN = 1
 BQ_FLAG_FUSED_XY = 2
+BQ_FLAG_GRAPH = 4
 BQ_TV_ISO, BQ_TV_ANISO = 0, 1
 BQ_SET_NONE, BQ_SET_NONNEG = 0, 1
 PASS_NAMES = ("zf", "xf", "yc", "xi", "zi", "xy", "vec")

@@ -62,7 +62,9 @@ class LSContext:
                  directions, precision: str = "f32", model: str = "ls",
                  tol: float = 1e-5, max_iter: int = 300, plain: bool = False,
                  fused_xy: bool = False, stream: torch.cuda.Stream | None = None,
-                 det_dist_um: float = 0.0):
+                 det_dist_um: float = 0.0, graphs: bool = False):
+        """graphs=True replays one captured BiCGSTAB iteration as a HIP graph
+        instead of launching its kernels one by one (same results)."""
         self._lib = L.load()
         self.N = int(N)
         self.precision = precision
@@ -75,7 +77,8 @@ class LSContext:
                    L.BQ_F32 if precision == "f32" else L.BQ_F64,
                    L.BQ_MODEL_LS if model == "ls" else L.BQ_MODEL_BORN,
                    float(tol), int(max_iter),
-                   (L.BQ_FLAG_PLAIN if plain else 0) | (L.BQ_FLAG_FUSED_XY if fused_xy else 0),
+                   (L.BQ_FLAG_PLAIN if plain else 0) | (L.BQ_FLAG_FUSED_XY if fused_xy else 0)
+                   | (L.BQ_FLAG_GRAPH if graphs else 0),
                    float(det_dist_um))
         ill = (L.Illum * self.L)(*[L.Illum(*row) for row in d])
         self._stream = stream

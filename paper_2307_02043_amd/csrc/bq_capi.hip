@@ -54,7 +54,13 @@ bq_status hip_err(bq_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_err(c, e_, #call);  \
   } while (0)
 
+void drop_graphs(bq_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
 void free_batch(bq_ctx* c) {
+  drop_graphs(c);
   for (auto& p : c->f) { if (p) (void)hipFree(p); p = nullptr; }
   void** others[] = {&c->zh, &c->xh, &c->rdet, (void**)&c->inc, (void**)&c->state,
                      (void**)&c->part_mv, (void**)&c->part_vec, (void**)&c->part_det};
@@ -182,6 +188,50 @@ void det_adjoint(bq_ctx* c, int nb) {
     plane_propagate<T>(nb, c->g.N, (C<T>*)c->rdet, (const C<T>*)c->twN, (const C<T>*)c->dettab, 1, c->stream);
 }
 
+// The captured iteration of a batched solve with these operands (captured on
+// first use); null when no graph can be made, and the caller then launches
+// the iteration kernel by kernel.  The graph holds kernels only (no memset
+// or copy nodes).
+template <typename F>
+hipGraphExec_t iteration_graph(bq_ctx* c, int B, const void* x, const void* e, const void* inc, F&& iteration) {
+  for (auto& g : c->graphs)
+    if (g.B == B && g.x == x && g.e == e && g.inc == inc) return g.exec;
+  if (!c->gstream) {
+    if (hipStreamCreate(&c->gstream) != hipSuccess) {
+      c->gstream = nullptr;
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if (hipEventCreateWithFlags(&c->gev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(c->gstream);
+      c->gstream = nullptr;
+      c->gev = nullptr;
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    iteration(c->gstream);
+    ok = hipStreamEndCapture(c->gstream, &graph) == hipSuccess && graph != nullptr;
+  }
+  ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (c->graphs.size() >= 4) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({B, x, e, inc, exec});
+  return exec;
+}
+
 // BiCGSTAB for B systems (I - G diag(x)) e_b = b_b.
 //   fwd:  b = u_in (generated), e = u_in on entry (written here)
 //   !fwd: b = e on entry (already computed)
@@ -227,53 +277,72 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
   sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
   if (bq_status s = check_launch(c, "init")) return s;
 
+  int& hint = c->hint[fwd ? 0 : 1];
+  const int max_loops = c->g.max_iter + 2;
+  int done_iters = 0;
+  // one iteration: p = r + beta (p - omega v) is formed inside the z-forward
+  // pass of A p; the scalar steps close each half
+  auto iteration = [&](hipStream_t s) {
+    a.mask = RUN_ACTIVE;
+    a.zf_mode = ZF_XP_UPD;
+    a.pio = va.p;
+    a.rvec = va.r;
+    a.vvec = va.v;
+    a.vin = va.p;
+    a.zi_mode = ZI_AV_RHAT;
+    a.vz = va.p;
+    a.rhat = va.rhat;
+    a.out = va.v;
+    a.out2 = nullptr;
+    green_apply<T>(a, s, &c->timer);
+    sc_alpha(B, c->state, c->part_mv, c->np_mv, s);
+    c->timer.start(P_VEC, s);
+    vec_s<T>(va, s);
+    c->timer.stop(s);
+    sc_s(B, c->state, c->part_vec, c->np_vec, s);
+    a.mask = RUN_ACTIVE_NOT_S;
+    a.zf_mode = ZF_XV;
+    a.vin = va.s;
+    a.zi_mode = ZI_AS_TS;
+    a.vz = va.s;
+    a.out = va.t;
+    green_apply<T>(a, s, &c->timer);
+    sc_omega(B, c->state, c->part_mv, c->np_mv, s);
+    c->timer.start(P_VEC, s);
+    vec_xr<T>(va, s);
+    c->timer.stop(s);
+    sc_beta(B, c->state, c->part_vec, c->np_vec, s);
+  };
+  // With BQ_FLAG_GRAPH, batched solves replay one captured iteration (not
+  // under per-pass timing, whose events sit between the passes)
+  hipGraphExec_t exec = nullptr;
+  hipStream_t s = c->stream;
+  if (!plain && !c->timer.on && (c->g.flags & BQ_FLAG_GRAPH)) exec = iteration_graph(c, B, x, e, inc, iteration);
+  if (exec) {
+    s = c->gstream;
+    HIPCHK(c, hipEventRecord(c->gev, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(s, c->gev, 0));
+  }
   // Host checks of the convergence flags (a device-to-host copy and a stream
   // synchronisation each): every iteration on the plain path; on the batched
   // path first after the iteration count of the previous solve of the same
   // kind, then every iteration, or every 4 iterations without history.
   // Systems that have stopped skip their work inside the kernels, so a late
-  // check costs only near-empty launches.
-  int& hint = c->hint[fwd ? 0 : 1];
-  const int max_loops = c->g.max_iter + 2;
-  int done_iters = 0;
+  // check costs only near-empty launches.  The last check synchronises the
+  // replay stream, so work the caller enqueues afterwards is ordered.
   for (int it = 0; it < max_loops;) {
     const int chunk = plain ? 1 : it == 0 && hint > 0 ? hint : hint > 0 ? 1 : 4;
     it += chunk;
     for (int k = 0; k < chunk; ++k) {
-      // p = r + beta (p - omega v) is formed inside the z-forward pass of A p
-      a.mask = RUN_ACTIVE;
-      a.zf_mode = ZF_XP_UPD;
-      a.pio = va.p;
-      a.rvec = va.r;
-      a.vvec = va.v;
-      a.vin = va.p;
-      a.zi_mode = ZI_AV_RHAT;
-      a.vz = va.p;
-      a.rhat = va.rhat;
-      a.out = va.v;
-      a.out2 = nullptr;
-      green_apply<T>(a, c->stream, &c->timer);
-      sc_alpha(B, c->state, c->part_mv, c->np_mv, c->stream);
-      c->timer.start(P_VEC, c->stream);
-      vec_s<T>(va, c->stream);
-      c->timer.stop(c->stream);
-      sc_s(B, c->state, c->part_vec, c->np_vec, c->stream);
-      a.mask = RUN_ACTIVE_NOT_S;
-      a.zf_mode = ZF_XV;
-      a.vin = va.s;
-      a.zi_mode = ZI_AS_TS;
-      a.vz = va.s;
-      a.out = va.t;
-      green_apply<T>(a, c->stream, &c->timer);
-      sc_omega(B, c->state, c->part_mv, c->np_mv, c->stream);
-      c->timer.start(P_VEC, c->stream);
-      vec_xr<T>(va, c->stream);
-      c->timer.stop(c->stream);
-      sc_beta(B, c->state, c->part_vec, c->np_vec, c->stream);
+      if (exec) {
+        HIPCHK(c, hipGraphLaunch(exec, s));
+      } else {
+        iteration(s);
+      }
     }
-    if (bq_status s = check_launch(c, "bicgstab iteration")) return s;
-    HIPCHK(c, hipMemcpyAsync(c->hstate, c->state, B * sizeof(SysState), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bq_status st = check_launch(c, "bicgstab iteration")) return st;
+    HIPCHK(c, hipMemcpyAsync(c->hstate, c->state, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     c->timer.maybe_collect();
     bool running = false;
     for (int b = 0; b < B; ++b) running |= (c->hstate[b].status == SYS_RUNNING);
@@ -578,7 +647,10 @@ bq_status create_tables(bq_ctx* c) {
 void destroy_ctx(bq_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
   free_batch(c);
+  if (c->gev) (void)hipEventDestroy(c->gev);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->ghat) (void)hipFree(c->ghat);
   if (c->twN) (void)hipFree(c->twN);
   if (c->twH) (void)hipFree(c->twH);

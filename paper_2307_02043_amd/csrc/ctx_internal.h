@@ -44,5 +44,20 @@ struct bq_ctx {
   // solve checks for convergence first after that many iterations, then
   // after every iteration (0: no history, check every 4)
   int hint[2] = {0, 0};
+  // BQ_FLAG_GRAPH: one BiCGSTAB iteration of the batched path captured as a
+  // HIP graph per (batch size, potential, solution, incident table) and
+  // replayed on a stream of the library's own (a graph cannot be captured
+  // on the legacy null stream a caller may use), ordered after the caller's
+  // stream by an event.  Dropped whenever the batch buffers change.
+  struct IterGraph {
+    int B;
+    const void* x;
+    const void* e;
+    const void* inc;
+    hipGraphExec_t exec;
+  };
+  std::vector<IterGraph> graphs;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev = nullptr;
 };
 

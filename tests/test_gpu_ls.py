@@ -322,3 +322,41 @@ def test_propagated_detector_matches_oracle(dev, N, prec, model):
     fl, _ = ctx.loss(torch.from_numpy(x).to(dev, rd), yt, idx, 0.5)
     assert abs(fl - fref) / fref < lim
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replayed_iterations_equal_kernel_by_kernel_launches(dev, prec):
+    """With BQ_FLAG_GRAPH, batched solves replay one captured BiCGSTAB
+    iteration as a HIP graph.  Repeated calls, with eager torch work and synchronisations between them,
+    a batch-size change (new graph, same buffers) and warm-started solves
+    into caller-owned fields give exactly the results of the path that
+    launches every kernel itself."""
+    x, y, dirs, idx, _, _ = _c1_reference()
+    N = x.shape[0]
+    rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    tol = 1e-13 if prec == "f64" else 1e-6
+    eager = _ctx(N, dirs, prec, tol=tol, max_iter=400)
+    graph = _ctx(N, dirs, prec, tol=tol, max_iter=400, graphs=True)
+    xt = torch.from_numpy(x).to(dev, rd)
+    yt = torch.from_numpy(y).to(dev, cd)
+    B = len(idx)
+    ref = {}
+    for nb in (B, 2):
+        ref[nb] = eager.grad(xt, yt[:nb], idx[:nb], 0.25)
+    for rep, nb in enumerate((B, B, 2, B, 2)):
+        g, f, info = graph.grad(xt, yt[:nb], idx[:nb], 0.25)
+        ge, fe, ie = ref[nb]
+        assert torch.equal(g, ge), (rep, nb)
+        assert f == fe and list(info.iters_fwd) == list(ie.iters_fwd), (rep, nb)
+        assert list(info.iters_adj) == list(ie.iters_adj), (rep, nb)
+        float((xt * 2.0).sum())  # eager work and a synchronisation between replays
+    for ctx in (eager, graph):
+        ctx.u = torch.zeros((B, N, N, N), dtype=cd, device=dev)
+        ctx.w = torch.zeros_like(ctx.u)
+        ctx.grad_ws(xt, yt, idx, 0.25, ctx.u, ctx.w, start=False)
+    ge, fe, _ = eager.grad_ws(1.02 * xt, yt, idx, 0.25, eager.u, eager.w, start=True)
+    g, f, _ = graph.grad_ws(1.02 * xt, yt, idx, 0.25, graph.u, graph.w, start=True)
+    assert torch.equal(g, ge) and f == fe
+    assert torch.equal(graph.u, eager.u) and torch.equal(graph.w, eager.w)
+    eager.close()
+    graph.close()
