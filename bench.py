@@ -151,6 +151,9 @@ def main():
                     help="workload whose weighted prox is timed alongside ('' to skip)")
     ap.add_argument("--qn-iters", type=int, default=9,
                     help="outer iterations of the quasi-Newton method timed alongside (0: skip)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="choose the launch shapes of the FFT passes by timing before the timed "
+                         "steps (bq_autotune; 0: default shapes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of this many MiB (reference for the "
                          "HBM traffic counters)")
@@ -194,6 +197,14 @@ def main():
     ctx = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol,
                     max_iter=w.max_iter)
     setup_s = time.perf_counter() - t
+    tune = None
+    if args.autotune:
+        t = time.perf_counter()
+        tune = ctx.autotune(B)
+        tune["s"] = round(time.perf_counter() - t, 2)
+        log(f"autotune: x tile rows {tune['x_tile_rows'] or 'default'}, z-forward threads "
+            f"{tune['zf_threads'] or 'default'} ({tune['ms_default']:.2f} -> {tune['ms_tuned']:.2f} ms "
+            f"per timed solve)")
     lib = L.load()
     xe = torch.from_numpy(0.5 * xt).to(dev, torch.float32)
     yt = torch.from_numpy(y).to(dev, torch.complex64)
@@ -377,6 +388,7 @@ def main():
                    "green_apps_per_step": apps / args.steps,
                    "bicgstab_iters_per_s": round(iters / elapsed, 1), "setup_s": round(setup_s, 2)},
         "passes_ms_per_step": {k: round(v / breakdown_steps, 3) for k, v in warm_ms.items()},
+        "autotune": tune,
         "prox": prox,
         "qn": qn,
         "detector_propagation": det,

@@ -205,6 +205,31 @@ typedef enum {
 bq_status bq_timing(bq_ctx* ctx, int enable);
 bq_status bq_timing_get(const bq_ctx* ctx, int pass, double* total_ms, long long* launches);
 
+/* Launch shapes of the Green's operator passes (implementation choices, no
+ * part of the paper's method): the rows per workgroup of the x passes and
+ * the threads per workgroup of the padded z-forward pass.  No value any
+ * call computes depends on them (neither pass forms a partial sum).
+ *
+ * bq_autotune times a short forward solve of B systems (tolerance 0, two
+ * BiCGSTAB iterations, a weak uniform potential, the first B illuminations)
+ * under each candidate shape, one at a time, keeps the fastest in the
+ * context for every later call, and reports it in *out (may be NULL; 0 in a
+ * field = the default shape).  It allocates the batch workspace for B
+ * systems (as a call with B systems would) and a temporary N^3 potential,
+ * synchronises the context stream, and leaves tolerance, iteration limit,
+ * per-pass timing and the convergence-check history as they were.
+ * bq_set_plan sets the shapes directly (0 = default).
+ * Errors: BQ_EINVAL (no context, B < 1, a shape not available for the
+ * grid and precision), BQ_ENOMEM, BQ_EDEVICE. */
+typedef struct {
+  int x_tile_rows;    /* rows per workgroup of the x passes (0: default)     */
+  int zf_threads;     /* threads of the padded z-forward pass (0: default)   */
+  double ms_default;  /* the timed solve with the default shapes             */
+  double ms_tuned;    /* the same with the chosen shapes                     */
+} bq_tune_result;
+bq_status bq_autotune(bq_ctx* ctx, int B, bq_tune_result* out);
+bq_status bq_set_plan(bq_ctx* ctx, int x_tile_rows, int zf_threads);
+
 /* ---------------------------------------------------------------------
  * Weighted proximal mapping of constrained TV
  * --------------------------------------------------------------------- */

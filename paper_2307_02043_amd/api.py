@@ -89,6 +89,18 @@ class LSContext:
         self._h = h
 
     # ------------------------------------------------------------------
+    def autotune(self, B: int) -> dict:
+        """Choose the launch shapes of the FFT passes for batches of B by
+        timing (bq_autotune); later calls compute the same values."""
+        r = L.TuneResult()
+        self._check(self._lib.bq_autotune(self._h, int(B), ct.byref(r)))
+        return {"x_tile_rows": r.x_tile_rows, "zf_threads": r.zf_threads,
+                "ms_default": r.ms_default, "ms_tuned": r.ms_tuned}
+
+    def set_plan(self, x_tile_rows: int = 0, zf_threads: int = 0):
+        """Set the launch shapes of the FFT passes directly (0 = default)."""
+        self._check(self._lib.bq_set_plan(self._h, int(x_tile_rows), int(zf_threads)))
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.bq_destroy(self._h)

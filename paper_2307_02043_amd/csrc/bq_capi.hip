@@ -138,6 +138,8 @@ PassArgs<T> pass_args(bq_ctx* c, int B, const C<double>* inc) {
   a.twH = (const C<T>*)c->twH;
   a.partial = c->part_mv;
   a.xy_fused = (c->g.flags & BQ_FLAG_FUSED_XY) ? 1 : 0;
+  a.xtile = c->plan_xtile;
+  a.zf_threads = c->plan_zf;
   return a;
 }
 
@@ -644,6 +646,91 @@ bq_status create_tables(bq_ctx* c) {
   return BQ_OK;
 }
 
+template <typename T>
+__global__ void k_fill_real(T* d, size_t n, T v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) d[i] = v;
+}
+
+// Times a short forward solve of B systems (tolerance 0, two iterations: the
+// solver-mode prologues and epilogues run) under each candidate launch shape
+// of the FFT passes, one knob at a time, and keeps the fastest.  Operands are
+// synthetic: a weak uniform potential and the first B illuminations.
+template <typename T>
+bq_status do_autotune(bq_ctx* c, int B, bq_tune_result* out) {
+  if (B < 1) return set_err(c, BQ_EINVAL, "B must be >= 1");
+  if (bq_status s = ensure_capacity(c, B)) return s;
+  std::vector<int> idx(B);
+  for (int b = 0; b < B; ++b) idx[b] = b % c->L;
+  T* x = nullptr;
+  HIPCHK(c, hipMalloc(&x, c->V * sizeof(T)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(x);
+    return set_err(c, BQ_EDEVICE, "event creation failed");
+  }
+  const bq_geom saved = c->g;
+  const int hint0 = c->hint[0], hint1 = c->hint[1];
+  const bool timer_on = c->timer.on;
+  c->g.tol = 0.0;
+  c->g.max_iter = 2;
+  c->timer.on = false;
+  const double k0 = 2.0 * M_PI / c->g.lambda0_um;
+  const T xval = (T)(k0 * k0 * 2.0 * c->g.n_b * 0.005);  // refractive-index contrast 0.005
+  hipLaunchKernelGGL((k_fill_real<T>), dim3(1024), dim3(256), 0, c->stream, x, c->V, xval);
+  bq_status st = upload_incident(c, idx.data(), B);
+  auto time_plan = [&](int xt, int zt, double* ms) -> bq_status {
+    c->plan_xtile = xt;
+    c->plan_zf = zt;
+    const int reps = 3;
+    for (int r = -1; r < reps; ++r) {  // one untimed run
+      if (r == 0 && hipEventRecord(e0, c->stream) != hipSuccess) return set_err(c, BQ_EDEVICE, "event record");
+      if (bq_status s2 = forward_fields<T>(c, x, B, c->f[F_U], false)) return s2;
+    }
+    float t = 0.f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+      return set_err(c, BQ_EDEVICE, "event timing");
+    *ms = t / reps;
+    return BQ_OK;
+  };
+  const int N = c->g.N;
+  double t_def = 0.0, best = 0.0;
+  int bx = 0, bz = 0;
+  if (st == BQ_OK) st = time_plan(0, 0, &t_def);
+  best = t_def;
+  for (int xt : {8, 16, 32}) {
+    if (st != BQ_OK || !xtile_valid<T>(N, xt)) continue;
+    double t = 0.0;
+    st = time_plan(xt, 0, &t);
+    if (st == BQ_OK && t < best) { best = t; bx = xt; }
+  }
+  for (int zt : {256, 1024}) {
+    if (st != BQ_OK || !zf_threads_valid<T>(N, zt)) continue;
+    double t = 0.0;
+    st = time_plan(bx, zt, &t);
+    if (st == BQ_OK && t < best) { best = t; bz = zt; }
+  }
+  c->g = saved;
+  c->hint[0] = hint0;
+  c->hint[1] = hint1;
+  c->timer.on = timer_on;
+  c->plan_xtile = st == BQ_OK ? bx : 0;
+  c->plan_zf = st == BQ_OK ? bz : 0;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(x);
+  if (st != BQ_OK) return st;
+  if (out) {
+    out->x_tile_rows = bx;
+    out->zf_threads = bz;
+    out->ms_default = t_def;
+    out->ms_tuned = best;
+  }
+  return BQ_OK;
+}
+
 void destroy_ctx(bq_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
@@ -745,6 +832,24 @@ bq_status bq_green_apply(bq_ctx* c, const void* v, void* out, int B, int adjoint
   if (!c) return BQ_EINVAL;
   return c->g.precision == BQ_F32 ? do_green<float>(c, v, out, B, adjoint)
                                   : do_green<double>(c, v, out, B, adjoint);
+}
+
+bq_status bq_autotune(bq_ctx* c, int B, bq_tune_result* out) {
+  if (!c) return BQ_EINVAL;
+  return c->g.precision == BQ_F32 ? do_autotune<float>(c, B, out) : do_autotune<double>(c, B, out);
+}
+
+bq_status bq_set_plan(bq_ctx* c, int x_tile_rows, int zf_threads) {
+  if (!c) return BQ_EINVAL;
+  const bool f32 = c->g.precision == BQ_F32;
+  const int N = c->g.N;
+  if (x_tile_rows != 0 && !(f32 ? xtile_valid<float>(N, x_tile_rows) : xtile_valid<double>(N, x_tile_rows)))
+    return set_err(c, BQ_EINVAL, "x tile rows not available for this grid and precision");
+  if (zf_threads != 0 && !(f32 ? zf_threads_valid<float>(N, zf_threads) : zf_threads_valid<double>(N, zf_threads)))
+    return set_err(c, BQ_EINVAL, "z-forward width not available for this grid and precision");
+  c->plan_xtile = x_tile_rows;
+  c->plan_zf = zf_threads;
+  return BQ_OK;
 }
 
 bq_status bq_timing(bq_ctx* c, int enable) {

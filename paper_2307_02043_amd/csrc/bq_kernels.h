@@ -78,6 +78,9 @@ template <typename T, int N> void launch_xi_stockham(const PassArgs<T>& a, hipSt
 template <typename T> int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm);
 template <typename T>
 int reg_num_partials(int N);
+// launch shapes the autotuner may choose (valid for this size and precision)
+template <typename T> bool xtile_valid(int N, int rows);
+template <typename T> bool zf_threads_valid(int N, int threads);
 template <typename T> int xy_fused_launch(const PassArgs<T>& a, hipStream_t st);
 template <typename T> int ghat_precompute(int N, double h, double kb, C<T>* out, hipStream_t st);
 template <typename T>

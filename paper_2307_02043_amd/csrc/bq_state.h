@@ -93,6 +93,9 @@ struct PassArgs {
   C<T>* out2;
   double* partial;             // B x NP x 4
   int xy_fused;                // use the LDS-resident plane pass when available
+  // launch shapes chosen by the autotuner (0: default); host side only
+  int xtile;                   // rows per workgroup of the x passes
+  int zf_threads;              // threads per workgroup of the padded z-forward pass
 };
 
 }  // namespace bq

@@ -44,6 +44,9 @@ struct bq_ctx {
   // solve checks for convergence first after that many iterations, then
   // after every iteration (0: no history, check every 4)
   int hint[2] = {0, 0};
+  // launch shapes of the FFT passes (0: default), set by bq_autotune or
+  // bq_set_plan; they change no value any call computes
+  int plan_xtile = 0, plan_zf = 0;
   // BQ_FLAG_GRAPH: one BiCGSTAB iteration of the batched path captured as a
   // HIP graph per (batch size, potential, solution, incident table) and
   // replayed on a stream of the library's own (a graph cannot be captured

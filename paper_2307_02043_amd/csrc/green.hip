@@ -17,6 +17,8 @@
 // ghat_P itself is precomputed here too (truncated Helmholtz kernel,
 // oversampled by Q per axis, cropped to the lags -N..N-1, transformed on the
 // 2N grid), in FP64 with the same FFT machinery.
+#include <type_traits>
+
 #include "bq_kernels.h"
 
 namespace bq {
@@ -146,9 +148,9 @@ __global__ void __launch_bounds__(NT) k_zf(PassArgs<T> a) {
 // Xf: x-direction forward FFTs of rows (pz, kz, y), both x parities.
 // grid (2 N^2 / TL, 1, B); writes xh[b][pz][px][kz][y][kx]
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, int TL = tile_w<T>(N)>
 __global__ void __launch_bounds__(NT) k_xf(PassArgs<T> a) {
-  constexpr int TL = tile_w<T>(N), LS = N + 1, TOT = TL * N, EPT = (TOT + NT - 1) / NT;
+  constexpr int LS = N + 1, TOT = TL * N, EPT = (TOT + NT - 1) / NT;
   __shared__ C<T> lds[TL * LS];
   __shared__ C<T> tw[N];
   __shared__ C<T> th[N];
@@ -262,9 +264,9 @@ __global__ void __launch_bounds__(NT) k_yc(PassArgs<T> a) {
 // Xi: x-direction inverse FFTs, x parities summed; writes back into zh.
 // grid (2 N^2 / TL, 1, B)
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, int TL = tile_w<T>(N)>
 __global__ void __launch_bounds__(NT) k_xi(PassArgs<T> a) {
-  constexpr int TL = tile_w<T>(N), LS = N + 1, TOT = TL * N, EPT = (TOT + NT - 1) / NT;
+  constexpr int LS = N + 1, TOT = TL * N, EPT = (TOT + NT - 1) / NT;
   __shared__ C<T> lds[TL * LS];
   __shared__ C<T> tw[N];
   __shared__ C<T> th[N];
@@ -493,16 +495,52 @@ int green_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-template <typename T, int N>
-void launch_xf_stockham(const PassArgs<T>& a, hipStream_t st) {
-  constexpr int TX = tile_w<T>(N);
-  hipLaunchKernelGGL((k_xf<T, N>), dim3(2 * N * N / TX, 1, a.B), dim3(NT), 0, st, a);
+// Rows per workgroup of the x passes: the default tile, or one the
+// autotuner chose among 8, 16 and 32 (a divisor of N within 64 KB of LDS).
+// Every tile computes the same values; only the launch shape changes.
+template <typename T, int N, int TL>
+constexpr bool xtile_ok() { return N % TL == 0 && TL * (N + 1) * (int)sizeof(C<T>) <= 65536; }
+
+template <typename T, int N, bool INV>
+static void launch_x_stockham(const PassArgs<T>& a, hipStream_t st) {
+  auto go = [&](auto tl) {
+    constexpr int TL = decltype(tl)::value;
+    if constexpr (INV)
+      hipLaunchKernelGGL((k_xi<T, N, TL>), dim3(2 * N * N / TL, 1, a.B), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_xf<T, N, TL>), dim3(2 * N * N / TL, 1, a.B), dim3(NT), 0, st, a);
+  };
+  switch (a.xtile) {
+    case 8: if constexpr (xtile_ok<T, N, 8>()) { go(std::integral_constant<int, 8>{}); return; } break;
+    case 16: if constexpr (xtile_ok<T, N, 16>()) { go(std::integral_constant<int, 16>{}); return; } break;
+    case 32: if constexpr (xtile_ok<T, N, 32>()) { go(std::integral_constant<int, 32>{}); return; } break;
+    default: break;
+  }
+  go(std::integral_constant<int, tile_w<T>(N)>{});
 }
 template <typename T, int N>
-void launch_xi_stockham(const PassArgs<T>& a, hipStream_t st) {
-  constexpr int TX = tile_w<T>(N);
-  hipLaunchKernelGGL((k_xi<T, N>), dim3(2 * N * N / TX, 1, a.B), dim3(NT), 0, st, a);
+void launch_xf_stockham(const PassArgs<T>& a, hipStream_t st) { launch_x_stockham<T, N, false>(a, st); }
+template <typename T, int N>
+void launch_xi_stockham(const PassArgs<T>& a, hipStream_t st) { launch_x_stockham<T, N, true>(a, st); }
+
+template <typename T>
+bool xtile_valid(int N, int tl) {
+  auto ok = [&](auto n) {
+    constexpr int NN = decltype(n)::value;
+    return (tl == 8 && xtile_ok<T, NN, 8>()) || (tl == 16 && xtile_ok<T, NN, 16>()) ||
+           (tl == 32 && xtile_ok<T, NN, 32>());
+  };
+  switch (N) {
+    case 16: return ok(std::integral_constant<int, 16>{});
+    case 32: return ok(std::integral_constant<int, 32>{});
+    case 64: return ok(std::integral_constant<int, 64>{});
+    case 128: return ok(std::integral_constant<int, 128>{});
+    case 256: return ok(std::integral_constant<int, 256>{});
+    default: return false;
+  }
 }
+template bool xtile_valid<float>(int, int);
+template bool xtile_valid<double>(int, int);
 #define BQ_XI(T, n) \
   template void launch_xf_stockham<T, n>(const PassArgs<T>&, hipStream_t); \
   template void launch_xi_stockham<T, n>(const PassArgs<T>&, hipStream_t);

@@ -380,9 +380,13 @@ __device__ inline void load_twtab_pad(C<T>* t, const C<T>* twH, int tid) {
 template <typename T, int N>
 constexpr int rtz() { return (N == 128 && sizeof(T) == 4) ? 1024 : RT; }
 
+// The z-forward pass writes no partial sums, so the autotuner may also run
+// it 1024 threads wide at other sizes (complex64, where the lines fit in LDS).
 template <typename T, int N>
-__global__ void __launch_bounds__((rtz<T, N>())) k_zf_p(PassArgs<T> a) {
-  constexpr int NTH = rtz<T, N>();
+constexpr bool zf_wide_ok() { return sizeof(T) == 4 && N <= 128 && PadCfg<N>::ok; }
+
+template <typename T, int N, int NTH = rtz<T, N>()>
+__global__ void __launch_bounds__(NTH) k_zf_p(PassArgs<T> a) {
   constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = NTH / R2, NI = R1 / R2;
   constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;  // H: nonzero inputs per thread
   constexpr uint32_t SZ = sizeof(C<T>);
@@ -526,9 +530,21 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
   constexpr int LPWY = RT / (PADY ? PadCfg<N>::R2 : RegCfg<N>::R2);
   const dim3 blk(RT);
   if (tm) tm->start(P_ZF, st);
-  if constexpr (PADZ)
-    hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPWZ, 1, a.B), dim3(NTZ), 0, st, a);
-  else
+  if constexpr (PADZ) {
+    if constexpr (zf_wide_ok<T, N>()) {
+      if (a.zf_threads == 1024 || a.zf_threads == RT) {  // tuned width
+        if (a.zf_threads == 1024)
+          hipLaunchKernelGGL((k_zf_p<T, N, 1024>), dim3(N * N / (1024 / PadCfg<N>::R2), 1, a.B), dim3(1024), 0,
+                             st, a);
+        else
+          hipLaunchKernelGGL((k_zf_p<T, N, RT>), dim3(N * N / (RT / PadCfg<N>::R2), 1, a.B), dim3(RT), 0, st, a);
+      } else {
+        hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPWZ, 1, a.B), dim3(NTZ), 0, st, a);
+      }
+    } else {
+      hipLaunchKernelGGL((k_zf_p<T, N>), dim3(N * N / LPWZ, 1, a.B), dim3(NTZ), 0, st, a);
+    }
+  } else
     hipLaunchKernelGGL((k_zf_r<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
   if (fused_xy) {
     if (tm) { tm->stop(st); tm->start(P_XY, st); }
@@ -572,6 +588,20 @@ template bool reg_supported<float>(int);
 template bool reg_supported<double>(int);
 template int reg_num_partials<float>(int);
 template int reg_num_partials<double>(int);
+
+template <typename T>
+bool zf_threads_valid(int N, int nth) {
+  if (nth != RT && nth != 1024) return false;
+  switch (N) {
+    case 16: return nth == RT || zf_wide_ok<T, 16>();
+    case 32: return nth == RT || zf_wide_ok<T, 32>();
+    case 64: return nth == RT || zf_wide_ok<T, 64>();
+    case 128: return nth == RT || zf_wide_ok<T, 128>();
+    default: return false;  // N = 256: parity-split z passes, one shape
+  }
+}
+template bool zf_threads_valid<float>(int, int);
+template bool zf_threads_valid<double>(int, int);
 template int reg_apply<float>(const PassArgs<float>&, hipStream_t, PassTimer*);
 template int reg_apply<double>(const PassArgs<double>&, hipStream_t, PassTimer*);
 

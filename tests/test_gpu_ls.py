@@ -360,3 +360,48 @@ def test_graph_replayed_iterations_equal_kernel_by_kernel_launches(dev, prec):
     assert torch.equal(graph.u, eager.u) and torch.equal(graph.w, eager.w)
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("case", ["c1_f64", "c1_f32", "c4_f32"])
+def test_launch_shapes_change_no_value(dev, case):
+    """Every launch shape the autotuner may choose (x-pass tile rows, width
+    of the z-forward pass) gives the same gradient bit for bit; the tuner
+    returns one of them; shapes not available are rejected."""
+    from paper_2307_02043_amd import BQError
+    if case.startswith("c1"):
+        x, y, dirs, idx, _, _ = _c1_reference()
+        prec = case[3:]
+        N = x.shape[0]
+        ctx = _ctx(N, dirs, prec, tol=1e-13 if prec == "f64" else 1e-6, max_iter=400)
+    else:
+        w = syn.WORKLOADS["c4_ls128_f32"]
+        prec, N = "f32", w.N
+        dirs = syn.workload_directions(w)
+        idx = syn.batch_indices(w)[:4]
+        x = 0.5 * syn.scattering_potential(syn.make_phantom(w))
+        ctx = _ctx(N, dirs, prec, tol=w.tol, max_iter=w.max_iter)
+        y = ctx.forward(torch.from_numpy(2 * x).to(dev, torch.float32), idx)[0].cpu().numpy()
+    rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    xt, yt = torch.from_numpy(x).to(dev, rd), torch.from_numpy(y).to(dev, cd)
+    g0, f0, i0 = ctx.grad(xt, yt, idx, 0.25)
+    tried = 0
+    for xr in (0, 8, 16, 32):
+        for zt in (0, 256, 1024):
+            try:
+                ctx.set_plan(xr, zt)
+            except BQError:
+                continue
+            g, f, info = ctx.grad(xt, yt, idx, 0.25)
+            assert torch.equal(g, g0) and f == f0, (xr, zt)
+            assert list(info.iters_fwd) == list(i0.iters_fwd), (xr, zt)
+            tried += 1
+    assert tried >= 3
+    with pytest.raises(BQError):
+        ctx.set_plan(5, 0)
+    with pytest.raises(BQError):
+        ctx.set_plan(0, 512)
+    r = ctx.autotune(len(idx))
+    assert r["ms_tuned"] <= r["ms_default"] and r["ms_default"] > 0
+    g, f, _ = ctx.grad(xt, yt, idx, 0.25)
+    assert torch.equal(g, g0) and f == f0
+    ctx.close()
