@@ -230,6 +230,16 @@ typedef struct {
 bq_status bq_autotune(bq_ctx* ctx, int B, bq_tune_result* out);
 bq_status bq_set_plan(bq_ctx* ctx, int x_tile_rows, int zf_threads);
 
+/* Systems per launch set of bq_forward, bq_fields, bq_loss, bq_grad and
+ * bq_grad_ws.  A batch larger than max_systems (0, the default: as many as
+ * the free device memory holds next to the context's own workspace, about
+ * 14 N^3 complex values per system) runs as consecutive sub-batches, each
+ * solved for its own contribution; per-system fields, images and
+ * iteration counts are the same, the gradient and loss are sums over the
+ * sub-batches (equal up to the order of the additions).
+ * Errors: BQ_EINVAL (no context, max_systems < 0). */
+bq_status bq_set_batch_limit(bq_ctx* ctx, int max_systems);
+
 /* ---------------------------------------------------------------------
  * Weighted proximal mapping of constrained TV
  * --------------------------------------------------------------------- */

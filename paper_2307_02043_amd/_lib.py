@@ -25,7 +25,7 @@ BQ_TIMING_ALL = (1 << len(PASS_NAMES)) - 1
 BQ_PROX_MAX_RANK = 8
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
-            "bq_grad", "bq_grad_ws", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_autotune", "bq_set_plan", "bq_prox_create", "bq_prox_destroy",
+            "bq_grad", "bq_grad_ws", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_autotune", "bq_set_plan", "bq_set_batch_limit", "bq_prox_create", "bq_prox_destroy",
             "bq_prox_last_error", "bq_wprox", "bq_qn_create", "bq_qn_destroy", "bq_qn_last_error",
             "bq_qn_step")
 
@@ -100,6 +100,7 @@ def load() -> ct.CDLL:
         "bq_timing_get": ([P, I, ct.POINTER(D), ct.POINTER(ct.c_longlong)], I),
         "bq_autotune": ([P, I, ct.POINTER(TuneResult)], I),
         "bq_set_plan": ([P, I, I], I),
+        "bq_set_batch_limit": ([P, I], I),
         "bq_prox_create": ([I, I, I, I, P, ct.POINTER(P)], I),
         "bq_prox_destroy": ([P], I),
         "bq_prox_last_error": ([P], ct.c_char_p),

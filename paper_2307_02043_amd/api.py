@@ -97,6 +97,11 @@ class LSContext:
         return {"x_tile_rows": r.x_tile_rows, "zf_threads": r.zf_threads,
                 "ms_default": r.ms_default, "ms_tuned": r.ms_tuned}
 
+    def set_batch_limit(self, max_systems: int = 0):
+        """Systems per launch set (0: as many as the free device memory
+        holds); larger batches run as consecutive sub-batches."""
+        self._check(self._lib.bq_set_batch_limit(self._h, int(max_systems)))
+
     def set_plan(self, x_tile_rows: int = 0, zf_threads: int = 0):
         """Set the launch shapes of the FFT passes directly (0 = default)."""
         self._check(self._lib.bq_set_plan(self._h, int(x_tile_rows), int(zf_threads)))

@@ -70,6 +70,34 @@ void free_batch(bq_ctx* c) {
   c->Bcap = 0;
 }
 
+// Device bytes of the batch workspace per system (see ensure_capacity).
+size_t per_system_bytes(const bq_ctx* c) {
+  const size_t N = (size_t)c->g.N;
+  return (8 + 2 + 4) * c->V * c->csz + N * N * c->csz + 3 * N * sizeof(C<double>) + sizeof(SysState) +
+         ((size_t)c->np_mv + (size_t)c->np_vec) * 4 * sizeof(double) + (size_t)c->np_det * sizeof(double);
+}
+
+// Systems per launch set: the whole batch unless its workspace would not fit
+// in the free device memory (with what the context holds already), or a
+// limit is set; the batch then runs as consecutive sub-batches, each one's
+// fields solved for its own contribution to the gradient.
+int batch_step(bq_ctx* c, int B, bool plain) {
+  if (plain) return 1;
+  long long lim = c->batch_limit;
+  if (lim <= 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      const size_t per = per_system_bytes(c);
+      const double avail = 0.9 * ((double)free_b + (double)c->Bcap * (double)per);
+      lim = (long long)(avail / (double)per);
+    } else {
+      (void)hipGetLastError();
+      lim = B;
+    }
+  }
+  return (int)std::max(1LL, std::min((long long)B, lim));
+}
+
 bq_status ensure_capacity(bq_ctx* c, int B) {
   if (B <= c->Bcap) return BQ_OK;
   free_batch(c);
@@ -416,13 +444,13 @@ bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out,
   if (bq_status s = check_batch(c, idx, B)) return s;
   if (!x || !out) return set_err(c, BQ_EINVAL, "null device pointer");
   const bool plain = (c->g.flags & BQ_FLAG_PLAIN) != 0;
-  if (bq_status s = ensure_capacity(c, plain ? 1 : B)) return s;
+  const int step = batch_step(c, B, plain);
+  if (bq_status s = ensure_capacity(c, step)) return s;
   std::vector<bq_solve_stats> stats(B);
   const int N = c->g.N;
   const size_t N2 = (size_t)N * N;
-  const int step = plain ? 1 : B;
   for (int b0 = 0; b0 < B; b0 += step) {
-    const int nb = plain ? 1 : B;
+    const int nb = std::min(step, B - b0);
     if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
     void* u = want_fields ? (void*)((C<T>*)out + (size_t)b0 * c->V) : c->f[F_U];
     int extra = c->g.model == BQ_MODEL_BORN ? 0 : 1;
@@ -458,15 +486,15 @@ bq_status do_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   if (bq_status s = check_batch(c, idx, B)) return s;
   if (!x || !y || !loss) return set_err(c, BQ_EINVAL, "null pointer");
   const bool plain = (c->g.flags & BQ_FLAG_PLAIN) != 0;
-  if (bq_status s = ensure_capacity(c, plain ? 1 : B)) return s;
+  const int step = batch_step(c, B, plain);
+  if (bq_status s = ensure_capacity(c, step)) return s;
   std::vector<bq_solve_stats> stats(B);
   const int N = c->g.N;
   const size_t N2 = (size_t)N * N;
   const bool born = c->g.model == BQ_MODEL_BORN;
   double total = 0.0;
-  const int step = plain ? 1 : B;
   for (int b0 = 0; b0 < B; b0 += step) {
-    const int nb = step;
+    const int nb = std::min(step, B - b0);
     if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
     const C<T>* field;
     int sub;
@@ -513,15 +541,15 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
     return set_err(c, ws && !w_io ? BQ_EINVAL : BQ_EUNSUPPORTED,
                    "field buffers: both u_io and w_io, LS model only");
   const bool plain = (c->g.flags & BQ_FLAG_PLAIN) != 0;
-  if (bq_status s = ensure_capacity(c, plain ? 1 : B)) return s;
+  const int step = batch_step(c, B, plain);
+  if (bq_status s = ensure_capacity(c, step)) return s;
   std::vector<bq_solve_stats> stats(B);
   const int N = c->g.N;
   const size_t N2 = (size_t)N * N;
   const bool born = c->g.model == BQ_MODEL_BORN;
   double total_loss = 0.0;
-  const int step = plain ? 1 : B;
   for (int b0 = 0; b0 < B; b0 += step) {
-    const int nb = step;
+    const int nb = std::min(step, B - b0);
     if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
     // forward field and detector residual r = S(u - u_in) - y
     const C<T>* field;
@@ -837,6 +865,13 @@ bq_status bq_green_apply(bq_ctx* c, const void* v, void* out, int B, int adjoint
 bq_status bq_autotune(bq_ctx* c, int B, bq_tune_result* out) {
   if (!c) return BQ_EINVAL;
   return c->g.precision == BQ_F32 ? do_autotune<float>(c, B, out) : do_autotune<double>(c, B, out);
+}
+
+bq_status bq_set_batch_limit(bq_ctx* c, int max_systems) {
+  if (!c) return BQ_EINVAL;
+  if (max_systems < 0) return set_err(c, BQ_EINVAL, "max_systems must be >= 0");
+  c->batch_limit = max_systems;
+  return BQ_OK;
 }
 
 bq_status bq_set_plan(bq_ctx* c, int x_tile_rows, int zf_threads) {

@@ -47,6 +47,9 @@ struct bq_ctx {
   // launch shapes of the FFT passes (0: default), set by bq_autotune or
   // bq_set_plan; they change no value any call computes
   int plan_xtile = 0, plan_zf = 0;
+  // systems per launch set (0: as many as the free device memory holds);
+  // larger batches run as consecutive sub-batches
+  int batch_limit = 0;
   // BQ_FLAG_GRAPH: one BiCGSTAB iteration of the batched path captured as a
   // HIP graph per (batch size, potential, solution, incident table) and
   // replayed on a stream of the library's own (a graph cannot be captured

@@ -405,3 +405,38 @@ def test_launch_shapes_change_no_value(dev, case):
     g, f, _ = ctx.grad(xt, yt, idx, 0.25)
     assert torch.equal(g, g0) and f == f0
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,model", [("f64", "ls"), ("f32", "ls"), ("f64", "born")])
+def test_sub_batches_equal_one_launch_set(dev, prec, model):
+    """A batch run as consecutive sub-batches (a limit of 2 and of 3 systems
+    per launch set for 4 systems) gives the same per-system fields, images
+    and iteration counts bit for bit, and the same gradient and loss up to
+    the order of the additions."""
+    x, y, dirs, idx, _, _ = _c1_reference()
+    N = x.shape[0]
+    rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    tol = 1e-13 if prec == "f64" else 1e-6
+    ctx = _ctx(N, dirs, prec, tol=tol, max_iter=400, model=model)
+    xt, yt = torch.from_numpy(x).to(dev, rd), torch.from_numpy(y).to(dev, cd)
+    g0, f0, i0 = ctx.grad(xt, yt, idx, 0.25)
+    h0, _ = ctx.forward(xt, idx)
+    u0, _ = ctx.fields(xt, idx)
+    l0, _ = ctx.loss(xt, yt, idx, 0.25)
+    lim = 1e-13 if prec == "f64" else 1e-6
+    for m in (2, 3):
+        ctx.set_batch_limit(m)
+        g, f, info = ctx.grad(xt, yt, idx, 0.25)
+        assert float(torch.linalg.norm(g - g0) / torch.linalg.norm(g0)) < lim, m
+        assert abs(f - f0) <= lim * abs(f0), m
+        assert list(info.iters_fwd) == list(i0.iters_fwd) and list(info.iters_adj) == list(i0.iters_adj)
+        h, _ = ctx.forward(xt, idx)
+        u, _ = ctx.fields(xt, idx)
+        assert torch.equal(h, h0) and torch.equal(u, u0), m
+        l, _ = ctx.loss(xt, yt, idx, 0.25)
+        assert abs(l - l0) <= lim * abs(l0), m
+    ctx.set_batch_limit(0)
+    from paper_2307_02043_amd import BQError
+    with pytest.raises(BQError):
+        ctx.set_batch_limit(-1)
+    ctx.close()
