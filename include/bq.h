@@ -210,7 +210,8 @@ bq_status bq_timing_get(const bq_ctx* ctx, int pass, double* total_ms, long long
  * the threads per workgroup of the padded z-forward pass.  No value any
  * call computes depends on them (neither pass forms a partial sum).
  *
- * bq_autotune times a short forward solve of B systems (tolerance 0, two
+ * bq_autotune times a short forward solve of B systems (or of the launch
+ * set a batch of B runs in, see bq_set_batch_limit; tolerance 0, two
  * BiCGSTAB iterations, a weak uniform potential, the first B illuminations)
  * under each candidate shape, one at a time, keeps the fastest in the
  * context for every later call, and reports it in *out (may be NULL; 0 in a

@@ -684,8 +684,9 @@ __global__ void k_fill_real(T* d, size_t n, T v) {
 // of the FFT passes, one knob at a time, and keeps the fastest.  Operands are
 // synthetic: a weak uniform potential and the first B illuminations.
 template <typename T>
-bq_status do_autotune(bq_ctx* c, int B, bq_tune_result* out) {
-  if (B < 1) return set_err(c, BQ_EINVAL, "B must be >= 1");
+bq_status do_autotune(bq_ctx* c, int B_in, bq_tune_result* out) {
+  if (B_in < 1) return set_err(c, BQ_EINVAL, "B must be >= 1");
+  const int B = batch_step(c, B_in, false);  // the launch set calls of B_in systems use
   if (bq_status s = ensure_capacity(c, B)) return s;
   std::vector<int> idx(B);
   for (int b = 0; b < B; ++b) idx[b] = b % c->L;
