@@ -58,6 +58,11 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.bq_create(ctypes.byref(g), bad, 1, None, ctypes.byref(out)) == L.BQ_EINVAL
     assert lib.bq_create(ctypes.byref(g), d, 0, None, ctypes.byref(out)) == L.BQ_EINVAL
     assert lib.bq_destroy(None) == L.BQ_OK
+    # entry points that need a context reject a null one before any device work
+    assert lib.bq_autotune(None, 4, None) == L.BQ_EINVAL
+    assert lib.bq_set_plan(None, 0, 0) == L.BQ_EINVAL
+    assert lib.bq_set_batch_limit(None, 0) == L.BQ_EINVAL
+    assert lib.bq_timing(None, 0) == L.BQ_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
