@@ -481,38 +481,64 @@ __device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti) {
 // the row index workgroup-uniform (scalar index arithmetic and branches).
 // f(row0, row1, two, x) gets a pair of rows, row1 = row0 + the stride of
 // the traversal, two = row1 exists; for_rows hands single rows to f(row, x).
+//
+// Workgroup h runs on XCD h mod 8, and each XCD has its own L2.  With a grid
+// that is a multiple of 8, XCD j takes the contiguous rows [j nrows / 8,
+// (j + 1) nrows / 8) and its G / 8 workgroups stride through them, so the
+// neighbouring rows a stencil reads (y +- 1 in the same step, z +- 1 a step
+// or two later) are fetched into the same L2 rather than from HBM again by
+// another XCD.  Other grids take every row in one range.
 // ---------------------------------------------------------------------------
+constexpr unsigned NUM_XCD = 8;
+
+struct RowSlab {
+  unsigned r0, r1;  // rows of this workgroup's XCD
+  unsigned k, per;  // rank of the workgroup among them, their number
+};
+
+__device__ inline RowSlab row_slab(unsigned nrows) {
+  const unsigned G = gridDim.x;
+  if (G >= NUM_XCD && G % NUM_XCD == 0) {
+    const unsigned j = blockIdx.x % NUM_XCD;
+    return {(unsigned)((unsigned long long)nrows * j / NUM_XCD),
+            (unsigned)((unsigned long long)nrows * (j + 1) / NUM_XCD), blockIdx.x / NUM_XCD, G / NUM_XCD};
+  }
+  return {0u, nrows, blockIdx.x, G};
+}
+
 template <int WG, class F>
 __device__ inline void for_row_pairs(int nx, unsigned nrows, F&& f) {
+  const RowSlab sl = row_slab(nrows);
   if (nx >= WG) {
-    for (unsigned row0 = blockIdx.x; row0 < nrows; row0 += 2 * gridDim.x) {
-      const unsigned row1 = row0 + gridDim.x;
-      for (int x = threadIdx.x; x < nx; x += WG) f(row0, row1, row1 < nrows, x);
+    for (unsigned row0 = sl.r0 + sl.k; row0 < sl.r1; row0 += 2 * sl.per) {
+      const unsigned row1 = row0 + sl.per;
+      for (int x = threadIdx.x; x < nx; x += WG) f(row0, row1, row1 < sl.r1, x);
     }
   } else {
     const unsigned rps = (unsigned)(WG / nx), rl = threadIdx.x / (unsigned)nx;
     const int x = (int)(threadIdx.x - rl * (unsigned)nx);
-    const unsigned stride = gridDim.x * rps;
+    const unsigned stride = sl.per * rps;
     if (rl < rps)
-      for (unsigned rb = blockIdx.x * rps; rb < nrows; rb += 2 * stride) {
+      for (unsigned rb = sl.r0 + sl.k * rps; rb < sl.r1; rb += 2 * stride) {
         const unsigned row0 = rb + rl, row1 = row0 + stride;
-        if (row0 < nrows) f(row0, row1, row1 < nrows, x);
+        if (row0 < sl.r1) f(row0, row1, row1 < sl.r1, x);
       }
   }
 }
 
 template <int WG, class F>
 __device__ inline void for_rows(int nx, unsigned nrows, F&& f) {
+  const RowSlab sl = row_slab(nrows);
   if (nx >= WG) {
-    for (unsigned row = blockIdx.x; row < nrows; row += gridDim.x)
+    for (unsigned row = sl.r0 + sl.k; row < sl.r1; row += sl.per)
       for (int x = threadIdx.x; x < nx; x += WG) f(row, x);
   } else {
     const unsigned rps = (unsigned)(WG / nx), rl = threadIdx.x / (unsigned)nx;
     const int x = (int)(threadIdx.x - rl * (unsigned)nx);
     if (rl < rps)
-      for (unsigned rb = blockIdx.x * rps; rb < nrows; rb += gridDim.x * rps) {
+      for (unsigned rb = sl.r0 + sl.k * rps; rb < sl.r1; rb += sl.per * rps) {
         const unsigned row = rb + rl;
-        if (row < nrows) f(row, x);
+        if (row < sl.r1) f(row, x);
       }
   }
 }

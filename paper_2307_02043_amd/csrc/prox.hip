@@ -21,7 +21,10 @@
 // start theta), k_ssn (partials S_A, T_A at the current theta), k_dual
 // (x at the voxel and its three forward neighbours, P = Proj(R + sigma D x),
 // momentum), k_out.  One-workgroup scalar kernels reduce the partials in a
-// fixed order and run the Newton / bisection logic on the device.
+// fixed order and run the Newton / bisection logic on the device.  Without
+// u (metric tau I) x is pointwise in d and there is no root: one kernel,
+// k_dual0, carries the whole dual iteration, and k_out0 the output.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -53,6 +56,7 @@ struct ProxState {
   int overflow;       // a dual iteration needed more root passes than were launched
   double eps;         // unit roundoff of the image precision
   double t, mom;      // FISTA sequence t_k and the momentum (t_k - 1) / t_{k+1}
+  double tt[2];       // t_k of the metric-tau-I path, alternating between two slots
 };
 
 template <typename T>
@@ -369,6 +373,118 @@ void launch_out(bool has_u, bool nonneg, dim3 g, dim3 b, hipStream_t s, const Pr
   }
 }
 
+// Metric tau I (no u): x = Proj_C(v - (lambda / tau) d(R)) is pointwise in
+// d, so one kernel carries a whole dual iteration: x from R_k at the voxel
+// and at its three forward neighbours (a divergence each), P_k = Proj(R_k +
+// sigma D x), R_{k+1} = P_k + mom (P_k - P_{k-1}).  R_{k+1} goes to a second
+// buffer, since neighbouring threads still read R_k; P is read and written
+// only at the voxel and is updated in place.  The arithmetic of x, of the
+// projection and of the momentum is that of k_div / k_px_after_div /
+// k_dual, operation for operation, so x does not depend on which thread
+// forms it.
+//
+// x at (z, y, x); the three components of R at that voxel are returned in
+// c[] (the caller reuses them for the dual step).
+template <typename T, bool NONNEG>
+__device__ inline T x_tau(const ProxArgs<T>& p, const T* __restrict__ R, T lt, int z, int y, int x, size_t j,
+                          T* c) {
+  const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
+  const T* Rz = R;
+  const T* Ry = R + V;
+  const T* Rx = R + 2 * V;
+  const T zm = Rz[z > 0 ? j - sz : j + sz], zc = Rz[j];
+  const T ym = Ry[y > 0 ? j - sy : j + sy], yc = Ry[j];
+  const T xm = Rx[x > 0 ? j - 1 : j + 1], xc = Rx[j];
+  c[0] = zc; c[1] = yc; c[2] = xc;
+  T d = 0;
+  d += z > 0 ? zm : T(0);
+  d -= z < p.nz - 1 ? zc : T(0);
+  d += y > 0 ? ym : T(0);
+  d -= y < p.ny - 1 ? yc : T(0);
+  d += x > 0 ? xm : T(0);
+  d -= x < p.nx - 1 ? xc : T(0);
+  T w = p.v[j] - lt * d;
+  if constexpr (NONNEG) w = w > T(0) ? w : T(0);
+  return w;
+}
+
+// Each thread walks one (y, x) column through a chunk of zc planes, so x and
+// R at plane z + 1, formed for the z difference, are the next step's centre;
+// x at x + 1 is the next lane's centre (a cross-lane shift; the last lane of
+// a wave forms it itself).  Traversal "rows" are (chunk, y) pairs, so rows
+// y and y + 1 of one chunk are neighbours in the XCD row slabs.
+//
+// par: slot of t_k in the state (t_{k+1} is written to the other slot by
+// one thread; no other thread reads that slot in this launch)
+template <typename T, bool NONNEG>
+__global__ void __launch_bounds__(PX_WG) k_dual0(ProxArgs<T> p, const T* __restrict__ Rin, T* __restrict__ Rout,
+                                                 int par, int zc) {
+  const double t = p.st->tt[par];
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  const T mom = (T)((t - 1.0) / tn);
+  if (blockIdx.x == 0 && threadIdx.x == 0) p.st->tt[par ^ 1] = tn;
+  const T lt = (T)(p.st->lam / p.st->tau);
+  const T sig = (T)p.sigma;
+  const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
+  const unsigned nchunk = (unsigned)((p.nz + zc - 1) / zc);
+  const bool last_lane = (threadIdx.x & 63) == 63;
+  for_rows<PX_WG>(p.nx, nchunk * (unsigned)p.ny, [&](unsigned row, int x) {
+    const int ch = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)ch * (unsigned)p.ny);
+    const int z0 = ch * zc, z1 = min(z0 + zc, p.nz);
+    const bool hy = y < p.ny - 1, hx = x < p.nx - 1;
+    size_t i = ((size_t)z0 * p.ny + y) * p.nx + x;
+    T rc[3], rn[3], ry[3], rx[3];
+    T xc = x_tau<T, NONNEG>(p, Rin, lt, z0, y, x, i, rc);
+    for (int z = z0; z < z1; ++z) {
+      // at the high faces the forward neighbour is replaced by the backward
+      // one (every dimension is >= 2) and its difference discarded below
+      const bool hz = z < p.nz - 1;
+      const T xz = x_tau<T, NONNEG>(p, Rin, lt, hz ? z + 1 : z - 1, y, x, hz ? i + sz : i - sz, rn);
+      const T xy = x_tau<T, NONNEG>(p, Rin, lt, z, hy ? y + 1 : y - 1, x, hy ? i + sy : i - sy, ry);
+      T xx = __shfl_down(xc, 1, 64);
+      if (last_lane && hx) xx = x_tau<T, NONNEG>(p, Rin, lt, z, y, x + 1, i + 1, rx);
+      const T gz = hz ? xz - xc : T(0);
+      const T gy = hy ? xy - xc : T(0);
+      const T gx = hx ? xx - xc : T(0);
+      T qz = rc[0] + sig * gz;
+      T qy = rc[1] + sig * gy;
+      T qx = rc[2] + sig * gx;
+      if (p.iso) {
+        const T n = sqrt(qz * qz + qy * qy + qx * qx);
+        if (n > T(1)) {
+          const T inv = T(1) / n;
+          qz *= inv; qy *= inv; qx *= inv;
+        }
+      } else {
+        qz = fmin(fmax(qz, T(-1)), T(1));
+        qy = fmin(fmax(qy, T(-1)), T(1));
+        qx = fmin(fmax(qx, T(-1)), T(1));
+      }
+      const T oz = nt_ld(&p.P[i]), oy = nt_ld(&p.P[V + i]), ox = nt_ld(&p.P[2 * V + i]);
+      nt_st(&p.P[i], qz); nt_st(&p.P[V + i], qy); nt_st(&p.P[2 * V + i], qx);
+      nt_st(&Rout[i], qz + mom * (qz - oz));
+      nt_st(&Rout[V + i], qy + mom * (qy - oy));
+      nt_st(&Rout[2 * V + i], qx + mom * (qx - ox));
+      xc = xz;
+      rc[0] = rn[0]; rc[1] = rn[1]; rc[2] = rn[2];
+      i += sz;
+    }
+  });
+}
+
+// x(Q) = Proj_C(v - (lambda / tau) d(Q)) for the metric tau I
+template <typename T, bool NONNEG>
+__global__ void __launch_bounds__(PX_WG) k_out0(ProxArgs<T> p, const T* __restrict__ Q) {
+  const T lt = (T)(p.st->lam / p.st->tau);
+  const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
+  for_rows<PX_WG>(p.nx, nrows, [&](unsigned row, int x) {
+    const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
+    const size_t i = (size_t)row * p.nx + x;
+    T c[3];
+    p.x_out[i] = x_tau<T, NONNEG>(p, Q, lt, z, y, x, i, c);
+  });
+}
+
 template <typename T>
 __global__ void k_fill(T* d, size_t n, T val) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -387,6 +503,7 @@ __global__ void k_px_init(ProxState* st, double tau, double lam, int has_u, int 
   s.theta = 0.0;
   s.done = 1;
   s.t = 1.0;
+  s.tt[0] = s.tt[1] = 1.0;
   *st = s;
 }
 
@@ -401,6 +518,7 @@ thread_local std::string g_prox_create_error;
 int px_grid(size_t V) {
   size_t g = (V + PX_WG * 4 - 1) / (PX_WG * 4);
   if (g > 2048) g = 2048;
+  if (g >= NUM_XCD) g = (g + NUM_XCD - 1) / NUM_XCD * NUM_XCD;  // one row slab per XCD
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -490,6 +608,93 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
   return BQ_OK;
 }
 
+// Metric tau I: one fused kernel per dual iteration (k_dual0), R_k and
+// R_{k+1} alternating between p->R and p->R2.  Two dual iterations are
+// captured as one graph (even: R -> R2, t in slot 0; odd: R2 -> R, slot 1)
+// and replayed; an odd count ends with one even iteration launched alone.
+template <typename T>
+bq_status run_wprox_tau(bq_prox* p, const void* v, double tau, double lam, int tv, int cset, int n_iter,
+                        void* x_out, void* P_io, bq_prox_stats* stats) {
+  const size_t V = p->V;
+  const hipStream_t s = p->own;
+  const dim3 g(p->np), b(PX_WG);
+  if (!p->R2 && hipMalloc(&p->R2, 3 * V * sizeof(T)) != hipSuccess) {
+    p->R2 = nullptr;
+    (void)hipGetLastError();
+    p->err = "out of device memory";
+    return BQ_ENOMEM;
+  }
+  ProxArgs<T> a{};
+  a.nz = p->nz; a.ny = p->ny; a.nx = p->nx; a.V = V;
+  a.v = (const T*)v;
+  a.P = P_io ? (T*)P_io : (T*)p->P;
+  a.x_out = (T*)x_out;
+  a.st = p->st;
+  a.iso = (tv == BQ_TV_ISO);
+  a.sigma = tau / (4.0 * 3.0 * lam);  // as in the rank-one path
+  const bool nonneg = (cset == BQ_SET_NONNEG);
+  T* R0 = (T*)p->R;
+  T* R1 = (T*)p->R2;
+  const double eps = sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+  hipLaunchKernelGGL(k_px_init, dim3(1), dim3(64), 0, s, p->st, tau, lam, 0, nonneg ? 1 : 0, eps);
+  if (!P_io) hipLaunchKernelGGL((k_fill<T>), dim3(1024), dim3(256), 0, s, a.P, 3 * V, T(0));  // P_0 = 0
+  if (hipMemcpyAsync(R0, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {  // R_1 = P_0
+    p->err = "copy of the starting dual point failed";
+    return BQ_EDEVICE;
+  }
+  // z chunk per thread: about 2^18 columns-times-chunks in flight (8 planes
+  // at 128^3, 32 at 256^3), at least 2; the grid covers the (chunk, y) rows
+  int zc = 2;
+  while (zc < 32 && (size_t)zc * 2 * 262144 <= V) zc *= 2;
+  const size_t rows = (size_t)((p->nz + zc - 1) / zc) * p->ny;
+  const size_t rps = p->nx >= PX_WG ? 1 : (size_t)(PX_WG / p->nx);
+  size_t g0 = std::min<size_t>((rows + rps - 1) / rps, 2048);
+  if (g0 >= NUM_XCD) g0 = (g0 + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+  const dim3 gd((unsigned)g0);
+  auto dual = [&](const T* rin, T* rout, int par) {
+    if (nonneg) hipLaunchKernelGGL((k_dual0<T, true>), gd, b, 0, s, a, rin, rout, par, zc);
+    else hipLaunchKernelGGL((k_dual0<T, false>), gd, b, 0, s, a, rin, rout, par, zc);
+  };
+  if (n_iter >= 2) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      dual(R0, R1, 0);
+      dual(R1, R0, 1);
+      ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
+    }
+    ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    for (int k = 0; ok && k < n_iter / 2; ++k) ok = hipGraphLaunch(exec, s) == hipSuccess;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+      (void)hipGetLastError();
+      p->err = "graph capture or launch of the dual iteration failed";
+      return BQ_EDEVICE;
+    }
+  }
+  if (n_iter % 2) dual(R0, R1, 0);
+  // x(P_K)
+  if (nonneg) hipLaunchKernelGGL((k_out0<T, true>), g, b, 0, s, a, (const T*)a.P);
+  else hipLaunchKernelGGL((k_out0<T, false>), g, b, 0, s, a, (const T*)a.P);
+  if (hipGetLastError() != hipSuccess) {
+    p->err = "kernel launch failed";
+    return BQ_EDEVICE;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    p->err = "device error in the proximal mapping";
+    return BQ_EDEVICE;
+  }
+  if (stats) {  // no root to find
+    stats->newton_total = 0;
+    stats->newton_max = 0;
+    stats->beta_last = 0.0;
+    stats->phi_last = 0.0;
+  }
+  return BQ_OK;
+}
+
 template <typename T>
 bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
                     int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
@@ -498,6 +703,7 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
     p->err = "stream synchronisation failed";
     return BQ_EDEVICE;
   }
+  if (!u) return run_wprox_tau<T>(p, v, tau, lam, tv, cset, n_iter, x_out, P_io, stats);
   ProxState hs{};
   const bq_status st = run_with_pass_budget(
       p, P_io, 3 * p->V * sizeof(T), u != nullptr && cset == BQ_SET_NONNEG, p->ssn_slots, p->max_passes - 1,
@@ -523,7 +729,7 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
 
 void free_prox(bq_prox* p) {
   if (!p) return;
-  void* ptrs[] = {p->a, p->P, p->R, p->xbuf, p->partial, p->st, p->rst, p->Pbak};
+  void* ptrs[] = {p->a, p->P, p->R, p->R2, p->xbuf, p->partial, p->st, p->rst, p->Pbak};
   for (void* q : ptrs) if (q) (void)hipFree(q);
   if (p->ev) (void)hipEventDestroy(p->ev);
   if (p->own) (void)hipStreamDestroy(p->own);

@@ -26,6 +26,7 @@ struct bq_prox {
   void* xbuf = nullptr;          // x(R) for metrics of rank >= 2
   double* partial = nullptr;     // np x PX_PART doubles
   void* Pbak = nullptr;          // copy of a caller's starting dual point (3V), for a rerun
+  void* R2 = nullptr;            // second momentum buffer (3V) of the metric-tau-I path, on first use
   bq::ProxState* st = nullptr;
   bq::ProxRankState* rst = nullptr;
   int np = 0;

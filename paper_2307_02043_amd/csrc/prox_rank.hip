@@ -491,6 +491,7 @@ size_t prox_rank_state_bytes() { return sizeof(ProxRankState); }
 static int pr_grid(size_t V) {
   size_t g = (V + PR_WG * 4 - 1) / (PR_WG * 4);
   if (g > 2048) g = 2048;
+  if (g >= NUM_XCD) g = (g + NUM_XCD - 1) / NUM_XCD * NUM_XCD;  // one row slab per XCD
   if (g < 1) g = 1;
   return (int)g;
 }

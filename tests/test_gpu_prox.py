@@ -285,3 +285,52 @@ def test_wprox_row_lengths(dev, shape, r, tv):
     ref = tp.wprox(v, 0.7, U, 2e-3, tv, "nonneg", n_iter=20)
     got, info, _ = _run(dev, shape, "f64", v, 0.7, U, 2e-3, tv, "nonneg", 20)
     assert _rel(got, ref) < 1e-10, _rel(got, ref)
+
+
+# ---- metric tau I (no u): one fused kernel per dual iteration ---------------
+
+@pytest.mark.parametrize("n_iter", [0, 1, 2, 7, 20])
+@pytest.mark.parametrize("shape", [(3, 5, 300), (2, 3, 256), (4, 6, 128), (2, 2, 2), (5, 7, 9)])
+@pytest.mark.parametrize("tv,cset", [("iso", "nonneg"), ("aniso", "none")])
+def test_wprox_tau_metric_iteration_counts_and_rows(dev, n_iter, shape, tv, cset):
+    """Odd and even iteration counts (pairs of dual iterations replayed as one
+    graph, an odd count ending with one launch alone, zero iterations giving
+    x(P_0)) on rows longer than, equal to and shorter than a workgroup."""
+    v, _ = _inputs(shape, 41 + n_iter)
+    ref = tp.wprox(v, 0.9, None, 2e-3, tv, cset, n_iter=n_iter)
+    got, info, _ = _run(dev, shape, "f64", v, 0.9, None, 2e-3, tv, cset, n_iter)
+    assert _rel(got, ref) < 1e-10, _rel(got, ref)
+    assert info.newton_total == 0 and info.newton_max == 0
+    if cset == "nonneg":
+        assert np.all(got >= 0)
+
+
+def test_wprox_tau_metric_warm_start_dual_point(dev):
+    """The dual point left in P after K iterations is the oracle's P_K, and a
+    call started from it continues the oracle's sequence."""
+    shape = (9, 10, 11)
+    v, _ = _inputs(shape, 57)
+    x13, P13 = tp.wprox(v, 0.5, None, 1e-3, "iso", "nonneg", n_iter=13, return_dual=True)
+    got13, _, Pg = _run(dev, shape, "f64", v, 0.5, None, 1e-3, "iso", "nonneg", 13, P=np.zeros((3,) + shape))
+    assert _rel(got13, x13) < 1e-10
+    assert _rel(Pg, P13) < 1e-10
+    ref = tp.wprox(v, 0.5, None, 1e-3, "iso", "nonneg", n_iter=8, P0=P13)
+    got, _, _ = _run(dev, shape, "f64", v, 0.5, None, 1e-3, "iso", "nonneg", 8, P=Pg)
+    assert _rel(got, ref) < 1e-10, _rel(got, ref)
+
+
+def test_wprox_tau_metric_f32_and_repeatable(dev):
+    """FP32 at 64^3 within 2e-4 of the oracle; three calls on one object give
+    the same bits (the second momentum buffer and both t slots are set up
+    afresh by every call)."""
+    shape = (64, 64, 64)
+    v, _ = _inputs(shape, 63)
+    ref = tp.wprox(v, 1.0, None, 1e-3, "iso", "nonneg", n_iter=25)
+    from paper_2307_02043_amd import WProx
+    px = WProx(shape, "f32")
+    vt = torch.from_numpy(v).to(dev, torch.float32)
+    outs = [px(vt, 1.0, None, 1e-3, "iso", "nonneg", 25)[0].clone() for _ in range(3)]
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    assert _rel(outs[0].cpu().numpy().astype(np.float64), ref) < 2e-4
+    px.close()
