@@ -225,3 +225,22 @@ def test_256_prox_matches_oracle(dev):
                      "iso", "nonneg", K)
         assert _rel(x.cpu().numpy(), ref) < tol, prec
         px.close()
+
+
+@pytest.mark.parametrize("tv,cset,K,precs", [("iso", "nonneg", 5, ("f32", "f64")), ("aniso", "none", 4, ("f32",))])
+def test_256_prox_tau_metric_matches_oracle(dev, tv, cset, K, precs):
+    """Metric tau I at 256^3 (one fused kernel per dual iteration, 32-plane
+    z chunks, the production grid): odd K = two replayed pairs and one
+    launch alone, even K = pairs only."""
+    from paper_2307_02043_amd import WProx
+    w = syn.WORKLOADS["c5_ls256_f32"]
+    v, tau, _ = syn.prox_inputs(w)
+    ref = tvprox.wprox(v, tau, None, w.prox_lambda, tv, cset, n_iter=K)
+    for prec in precs:
+        tol = 2e-4 if prec == "f32" else 1e-10
+        rd = torch.float32 if prec == "f32" else torch.float64
+        px = WProx(v.shape, prec)
+        x, info = px(torch.from_numpy(v).to(dev, rd), tau, None, w.prox_lambda, tv, cset, K)
+        assert _rel(x.cpu().numpy(), ref) < tol, prec
+        assert info.newton_total == 0
+        px.close()
