@@ -80,10 +80,12 @@ size_t per_system_bytes(const bq_ctx* c) {
 // Systems per launch set: the whole batch unless its workspace would not fit
 // in the free device memory (with what the context holds already), or a
 // limit is set; the batch then runs as consecutive sub-batches, each one's
-// fields solved for its own contribution to the gradient.
+// fields solved for its own contribution to the gradient.  A batch the held
+// workspace already covers needs no new memory and no query of the device.
 int batch_step(bq_ctx* c, int B, bool plain) {
   if (plain) return 1;
   long long lim = c->batch_limit;
+  if (lim <= 0 && B <= c->Bcap) return B;
   if (lim <= 0) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
