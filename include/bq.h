@@ -295,8 +295,12 @@ const char* bq_prox_last_error(const bq_prox* p);
  * launched, the starting dual point is first copied to a 3 x image buffer
  * that the workspace allocates on first use (if that allocation fails, the
  * full passes are launched instead).
- * Errors: BQ_EINVAL (arguments), BQ_EDEVICE; BQ_NOTCONV if the root-find
- * hit its pass limit in some dual iteration (x is still returned). */
+ * With r = 0 the projection is pointwise and there is no root (st reports
+ * zero passes); the first such call allocates a second 3 x image buffer
+ * for the dual momentum, kept until bq_prox_destroy.
+ * Errors: BQ_EINVAL (arguments), BQ_ENOMEM (r = 0, that buffer),
+ * BQ_EDEVICE; BQ_NOTCONV if the root-find hit its pass limit in some dual
+ * iteration (x is still returned). */
 bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, double lambda, int tv,
                    int cset, int n_iter, void* x_out, void* P_io, bq_prox_stats* st);
 
