@@ -355,7 +355,7 @@ def main():
     # ---- outer iteration of the method on the same workload -----------------
     qn = None
     if args.qn_iters > 0:
-        qn = bench_qn(w, dev, xt, dirs, args.qn_iters, 1e3 * elapsed / args.steps)
+        qn = bench_qn(w, dev, xt, dirs, args.qn_iters, 1e3 * elapsed / args.steps, plan=tune)
 
     # ---- weighted TV prox (second kernel of the method) ---------------------
     prox = None
@@ -424,14 +424,15 @@ def bench_detprop(w, dev, xt, dirs, idx, scale, steps, base_ms, d_um=1.0):
     return {"det_dist_um": d_um, "ms_per_step": round(ms, 3), "exit_plane_ms_per_step": round(base_ms, 3)}
 
 
-def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):
+def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):
     """Outer iterations of Algorithm 4.1 (strategy I) on the workload's grid:
     S subsets of B illuminations (the first S B directions), x_0 = 0.5
     x_true, step 1/20, 50 dual iterations per WPM, FP32; three variants:
     SR1 metrics of Algorithm 4.2 (gamma 0.8, tau_max 1e8) with cold solves,
     the same with warm-started solves, and the first-order (alpha I)
     variant with warm-started solves.  Measurements from the library's FP32
-    forward model (tol 1e-6) without noise."""
+    forward model (tol 1e-6) without noise.  The LS context takes `plan`,
+    the launch shapes tuned for the gradient workload, when given."""
     import torch
 
     from paper_2307_02043_amd import LSContext, QNIteration, WProx
@@ -445,6 +446,8 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4):
         y[sub] = ls.forward(xtt, sub)[0]
     ls.close()
     ls = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol, max_iter=w.max_iter)
+    if plan:  # the launch shapes tuned for the gradient workload (same grid, batch and precision)
+        ls.set_plan(plan["x_tile_rows"], plan["zf_threads"])
     x = (0.5 * xtt).contiguous()
     g0, _, _ = ls.grad(x, y[subsets[0]], subsets[0], S / w.L)
     alpha = float(g0.abs().max()) / float(xtt.max())
