@@ -229,15 +229,6 @@ __device__ inline void px_step(ProxState& s, double SA, double TA, int max_passe
 
 __global__ void __launch_bounds__(256) k_px_after_div(ProxState* st, const double* part, int np, int max_passes) {
   __shared__ double scratch[4 * 4];
-  if (!st->has_u) {
-    if (threadIdx.x == 0) {
-      const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st->t * st->t));
-      st->mom = (st->t - 1.0) / tn;
-      st->t = tn;
-      st->done = 1;
-    }
-    return;
-  }
   double v[4];
   px_sum<0, 4>(part, np, v, scratch);
   if (threadIdx.x != 0) return;
@@ -351,26 +342,17 @@ __global__ void __launch_bounds__(PX_WG) k_out(ProxArgs<T> p) {
     p.x_out[i] = xval<T, HAS_U, NONNEG>(p, i, theta);
 }
 
-// launch k_dual / k_out specialised on whether u exists and on the constraint
+// launch k_dual / k_out of the rank-one path, specialised on the constraint
+// (without u the metric-tau-I path below runs instead)
 template <typename T>
-void launch_dual(bool has_u, bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
-  if (has_u) {
-    if (nonneg) hipLaunchKernelGGL((k_dual<T, true, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_dual<T, true, false>), g, b, 0, s, a);
-  } else {
-    if (nonneg) hipLaunchKernelGGL((k_dual<T, false, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_dual<T, false, false>), g, b, 0, s, a);
-  }
+void launch_dual(bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
+  if (nonneg) hipLaunchKernelGGL((k_dual<T, true, true>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_dual<T, true, false>), g, b, 0, s, a);
 }
 template <typename T>
-void launch_out(bool has_u, bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
-  if (has_u) {
-    if (nonneg) hipLaunchKernelGGL((k_out<T, true, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_out<T, true, false>), g, b, 0, s, a);
-  } else {
-    if (nonneg) hipLaunchKernelGGL((k_out<T, false, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_out<T, false, false>), g, b, 0, s, a);
-  }
+void launch_out(bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
+  if (nonneg) hipLaunchKernelGGL((k_out<T, true, true>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_out<T, true, false>), g, b, 0, s, a);
 }
 
 // Metric tau I (no u): x = Proj_C(v - (lambda / tau) d(R)) is pointwise in
@@ -523,8 +505,8 @@ int px_grid(size_t V) {
   return (int)g;
 }
 
-// One run of the iteration with `slots` root passes launched per dual
-// iteration; the final device state goes to *hs.
+// One run of the rank-one iteration (u not null) with `slots` root passes
+// launched per dual iteration; the final device state goes to *hs.
 template <typename T>
 bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
                          int n_iter, void* x_out, void* P_io, int slots, ProxState* hs_out) {
@@ -576,7 +558,7 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       primal();
-      launch_dual<T>(has_u, nonneg, g, b, s, a);
+      launch_dual<T>(nonneg, g, b, s, a);
       ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
     }
     ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -595,7 +577,7 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
     return BQ_EDEVICE;
   }
   primal();
-  launch_out<T>(has_u, nonneg, g, b, s, a);
+  launch_out<T>(nonneg, g, b, s, a);
   if (hipGetLastError() != hipSuccess) {
     p->err = "kernel launch failed";
     return BQ_EDEVICE;
