@@ -16,6 +16,8 @@ Contents (each function cites the passage of arXiv:2307.02043 it follows):
 * tvprox     -- discrete TV, its dual, the weighted projection onto the
                 nonnegative orthant under tau I + U U^T (Theorem 3.1) and the
                 fast dual projected gradient iteration of Section 4.1.
+* bqnpm      -- the SR1 metric of Algorithm 4.2 and the outer iteration of
+                Algorithm 4.1 over the two above.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test against a
 closed form, a brute-force or dense computation, or an invariant; the paper

@@ -211,3 +211,54 @@ def test_warm_started_gradient_equals_cold_gradient():
     assert np.linalg.norm(gw - gc) / np.linalg.norm(gc) < 1e-10
     assert abs(fw - fc) < 1e-10 * fc
     assert sum(s[0] + s[1] for s in stw) < sum(s[0] + s[1] for s in stc)
+
+
+@pytest.mark.parametrize("N", [7, 8, 13])
+def test_incident_field_is_the_plane_wave_of_the_background(N):
+    """The illumination of Section 6.1 is a plane wave in the background
+    medium: a unit-modulus field whose phase advances by k_b d_a h per voxel
+    along axis a (k_b = 2 pi n_b / lambda0, not the vacuum k0), that
+    satisfies the discrete Helmholtz equation of the background exactly, and
+    whose phase origin is the centre of the domain.  Each check fails for
+    one plausible misreading: k0 for k_b, a flipped or permuted direction
+    component, an origin at a corner or half a voxel off."""
+    geom = _geom(N)
+    h, kb = geom.h, 2 * math.pi * NB / LAM0
+    assert abs(geom.kb - kb) < 1e-12 * kb
+    d = np.array([0.31, -0.22, 0.0])
+    d[2] = math.sqrt(1 - d[0] ** 2 - d[1] ** 2)
+    u = lsmodel.incident_field(geom, tuple(d))
+    assert u.shape == (N, N, N)
+    assert np.max(np.abs(np.abs(u) - 1)) < 1e-14
+    # per-voxel phase advance along x (array axis 2), y (1), z (0)
+    for axis, comp in ((2, d[0]), (1, d[1]), (0, d[2])):
+        ratio = np.take(u, np.arange(1, N), axis=axis) / np.take(u, np.arange(N - 1), axis=axis)
+        assert np.max(np.abs(ratio - np.exp(1j * kb * comp * h))) < 1e-12
+    # the 7-point Laplacian of exp(i k.r) is exactly
+    # -sum_a (4/h^2) sin^2(k_a h / 2) times the field, and that factor tends
+    # to -k_b^2 as h -> 0 (O(h^2))
+    lap = (u[2:, 1:-1, 1:-1] + u[:-2, 1:-1, 1:-1] + u[1:-1, 2:, 1:-1] + u[1:-1, :-2, 1:-1]
+           + u[1:-1, 1:-1, 2:] + u[1:-1, 1:-1, :-2] - 6 * u[1:-1, 1:-1, 1:-1]) / h ** 2
+    fac = -sum(4 / h ** 2 * math.sin(kb * c * h / 2) ** 2 for c in d)
+    assert np.max(np.abs(lap - fac * u[1:-1, 1:-1, 1:-1])) < 1e-9 * kb ** 2
+    # (k_b h is about 2.1 here, a quarter wavelength per voxel in vacuum, so
+    # the O(h^2) term is about a quarter of k_b^2 at the grid's own spacing)
+    assert abs(fac + kb ** 2) < 0.3 * kb ** 2
+    # on finer grids the oracle's field's Laplacian tends to -k_b^2 u at O(h^2)
+    errs = []
+    for hh in (h / 8, h / 16):
+        g2 = lsmodel.Geometry(N=N, h=hh, lambda0=LAM0, n_b=NB)
+        w = lsmodel.incident_field(g2, tuple(d))
+        lw = (w[2:, 1:-1, 1:-1] + w[:-2, 1:-1, 1:-1] + w[1:-1, 2:, 1:-1] + w[1:-1, :-2, 1:-1]
+              + w[1:-1, 1:-1, 2:] + w[1:-1, 1:-1, :-2] - 6 * w[1:-1, 1:-1, 1:-1]) / hh ** 2
+        errs.append(np.max(np.abs(lw / w[1:-1, 1:-1, 1:-1] + kb ** 2)))
+    assert errs[0] < 0.02 * kb ** 2 and abs(errs[0] / errs[1] - 4) < 0.1, errs
+    # phase origin at the domain centre: u(-r) = conj(u(r)) for every voxel,
+    # and for odd N the centre voxel has phase 0
+    assert np.max(np.abs(u[::-1, ::-1, ::-1] - np.conj(u))) < 1e-12
+    if N % 2:
+        c = (N - 1) // 2
+        assert abs(u[c, c, c] - 1) < 1e-15
+    # a corner voxel sits at r = -(N-1)/2 h on every axis
+    corner = np.exp(-1j * kb * (N - 1) / 2 * h * d.sum())
+    assert abs(u[0, 0, 0] - corner) < 1e-12
