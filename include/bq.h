@@ -241,6 +241,31 @@ bq_status bq_set_plan(bq_ctx* ctx, int x_tile_rows, int zf_threads);
  * Errors: BQ_EINVAL (no context, max_systems < 0). */
 bq_status bq_set_batch_limit(bq_ctx* ctx, int max_systems);
 
+/* Breakdown test of BiCGSTAB (van der Vorst 1992, the solver of the
+ * Lippmann-Schwinger systems of Section 6): a system stops with status
+ * "breakdown" (BQ_BREAKDOWN from the call) when |rho| = |<rhat, r>|,
+ * |<rhat, A p>| or |omega| falls below floor; its iterate is kept as it was
+ * at that point.  Default 1e-300 (only exact or near-exact vanishing).  A
+ * larger floor stops solves early where these scalars become small
+ * relative to the problem's scale.  Applies to later calls.
+ * Errors: BQ_EINVAL (no context, floor negative or not finite). */
+bq_status bq_set_breakdown_floor(bq_ctx* ctx, double floor);
+
+/* State of a context, for callers that manage memory and graph replay.
+ * Errors: BQ_EINVAL (null argument). */
+typedef struct {
+  int batch_capacity;       /* systems the held batch workspace covers (0: none) */
+  int x_tile_rows;          /* launch shape in use (0: default)                  */
+  int zf_threads;           /* launch shape in use (0: default)                  */
+  int graphs_cached;        /* captured BiCGSTAB iteration graphs held (<= 4)    */
+  long long graph_captures; /* iteration graphs captured since creation; a
+                               graph is captured again after a change of batch
+                               buffers, potential, incident table or launch
+                               shapes (bq_set_plan); bq_autotune drops all     */
+  double breakdown_floor;   /* see bq_set_breakdown_floor                        */
+} bq_ctx_info;
+bq_status bq_get_info(const bq_ctx* ctx, bq_ctx_info* out);
+
 /* ---------------------------------------------------------------------
  * Weighted proximal mapping of constrained TV
  * --------------------------------------------------------------------- */

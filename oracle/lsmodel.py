@@ -87,11 +87,12 @@ def incident_field(geom: Geometry, direction) -> np.ndarray:
     return np.exp(1j * ph)
 
 
-def bicgstab(apply_A, b, x0, tol, max_iter):
+def bicgstab(apply_A, b, x0, tol, max_iter, breakdown=1e-300):
     """BiCGSTAB for A e = b (van der Vorst 1992), complex FP64.
 
     Inner product <a, b> = sum conj(a) b.  Returns (e, iterations, status,
-    final relative recursive residual).
+    final relative recursive residual).  The solve stops with status
+    BREAKDOWN when |rho|, |<rhat, v>| or |omega| falls below ``breakdown``.
     """
     e = np.array(x0, dtype=np.complex128, copy=True)
     r = b - apply_A(e)
@@ -107,12 +108,16 @@ def bicgstab(apply_A, b, x0, tol, max_iter):
     p = np.zeros_like(r)
     for it in range(1, max_iter + 1):
         rho_new = np.vdot(rhat, r)
-        if abs(rho_new) < 1e-300:
+        if abs(rho_new) < breakdown:
             return e, it - 1, BREAKDOWN, res
         beta = (rho_new / rho) * (alpha / omega)
         p = r + beta * (p - omega * v)
         v = apply_A(p)
-        alpha = rho_new / np.vdot(rhat, v)
+        rv = np.vdot(rhat, v)
+        if abs(rv) < breakdown or rv == 0:
+            # counted as an iteration: its product A p was formed
+            return e, it, BREAKDOWN, res
+        alpha = rho_new / rv
         s = r - alpha * v
         res_s = np.linalg.norm(s) / bnorm
         if res_s <= tol:
@@ -127,7 +132,7 @@ def bicgstab(apply_A, b, x0, tol, max_iter):
         res = np.linalg.norm(r) / bnorm
         if res <= tol:
             return e, it, CONVERGED, res
-        if abs(omega) < 1e-300:
+        if abs(omega) < breakdown:
             return e, it, BREAKDOWN, res
     return e, max_iter, NOT_CONVERGED, res
 
@@ -168,13 +173,15 @@ class LSModel:
         return out
 
     # solves ----------------------------------------------------------------
-    def solve_forward(self, x, uin, tol, max_iter, e0=None):
+    def solve_forward(self, x, uin, tol, max_iter, e0=None, breakdown=1e-300):
         """(I - G diag(x)) u = u_in, started from u_in (or from e0)."""
-        return bicgstab(lambda e: e - self.G(x * e), uin, uin if e0 is None else e0, tol, max_iter)
+        return bicgstab(lambda e: e - self.G(x * e), uin, uin if e0 is None else e0, tol, max_iter,
+                        breakdown)
 
-    def solve_adjoint(self, x, z, tol, max_iter, e0=None):
+    def solve_adjoint(self, x, z, tol, max_iter, e0=None, breakdown=1e-300):
         """(I - G^H diag(x)) w = z, started from z (or from e0)."""
-        return bicgstab(lambda e: e - self.GH(x * e), z, z if e0 is None else e0, tol, max_iter)
+        return bicgstab(lambda e: e - self.GH(x * e), z, z if e0 is None else e0, tol, max_iter,
+                        breakdown)
 
     # model -----------------------------------------------------------------
     def forward(self, x, directions, idx, tol, max_iter, model="ls"):

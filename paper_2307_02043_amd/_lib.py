@@ -25,7 +25,8 @@ BQ_TIMING_ALL = (1 << len(PASS_NAMES)) - 1
 BQ_PROX_MAX_RANK = 8
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
-            "bq_grad", "bq_grad_ws", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_autotune", "bq_set_plan", "bq_set_batch_limit", "bq_prox_create", "bq_prox_destroy",
+            "bq_grad", "bq_grad_ws", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_autotune", "bq_set_plan", "bq_set_batch_limit",
+            "bq_set_breakdown_floor", "bq_get_info", "bq_prox_create", "bq_prox_destroy",
             "bq_prox_last_error", "bq_wprox", "bq_qn_create", "bq_qn_destroy", "bq_qn_last_error",
             "bq_qn_step")
 
@@ -44,6 +45,12 @@ class Illum(ct.Structure):
 class TuneResult(ct.Structure):
     _fields_ = [("x_tile_rows", ct.c_int), ("zf_threads", ct.c_int), ("ms_default", ct.c_double),
                 ("ms_tuned", ct.c_double)]
+
+
+class CtxInfo(ct.Structure):
+    _fields_ = [("batch_capacity", ct.c_int), ("x_tile_rows", ct.c_int), ("zf_threads", ct.c_int),
+                ("graphs_cached", ct.c_int), ("graph_captures", ct.c_longlong),
+                ("breakdown_floor", ct.c_double)]
 
 
 class SolveStats(ct.Structure):
@@ -101,6 +108,8 @@ def load() -> ct.CDLL:
         "bq_autotune": ([P, I, ct.POINTER(TuneResult)], I),
         "bq_set_plan": ([P, I, I], I),
         "bq_set_batch_limit": ([P, I], I),
+        "bq_set_breakdown_floor": ([P, D], I),
+        "bq_get_info": ([P, ct.POINTER(CtxInfo)], I),
         "bq_prox_create": ([I, I, I, I, P, ct.POINTER(P)], I),
         "bq_prox_destroy": ([P], I),
         "bq_prox_last_error": ([P], ct.c_char_p),

@@ -106,6 +106,17 @@ class LSContext:
         """Set the launch shapes of the FFT passes directly (0 = default)."""
         self._check(self._lib.bq_set_plan(self._h, int(x_tile_rows), int(zf_threads)))
 
+    def set_breakdown_floor(self, floor: float):
+        """|rho|, |<rhat, A p>| or |omega| below floor stops a BiCGSTAB
+        solve with status breakdown (default 1e-300)."""
+        self._check(self._lib.bq_set_breakdown_floor(self._h, float(floor)))
+
+    def info(self) -> dict:
+        """Workspace capacity, launch shapes and graph-cache counters."""
+        r = L.CtxInfo()
+        self._check(self._lib.bq_get_info(self._h, ct.byref(r)))
+        return {f: getattr(r, f) for f, _ in L.CtxInfo._fields_}
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.bq_destroy(self._h)
@@ -131,6 +142,14 @@ class LSContext:
         if v.dtype != self.cdtype or v.device.type != "cuda" or tuple(v.shape) != tuple(shape):
             raise ValueError(f"expected {self.cdtype} cuda tensor of shape {shape}")
         return v.contiguous()
+
+    def _out(self, out: torch.Tensor | None, shape) -> torch.Tensor:
+        if out is None:
+            return torch.empty(shape, dtype=self.rdtype, device=self.device)
+        if (out.dtype != self.rdtype or out.device.type != "cuda" or tuple(out.shape) != tuple(shape)
+                or not out.is_contiguous()):
+            raise ValueError(f"out must be a contiguous {self.rdtype} cuda tensor of shape {shape}")
+        return out
 
     @staticmethod
     def _idx(idx):
@@ -162,7 +181,7 @@ class LSContext:
         x = self._real(x, (N, N, N))
         a, pidx, B = self._idx(idx)
         y = self._cplx(y, (B, N, N))
-        g = torch.empty((N, N, N), dtype=self.rdtype, device=x.device) if out is None else out
+        g = self._out(out, (N, N, N))
         loss = ct.c_double(0.0)
         st = (L.SolveStats * B)()
         s = self._check(self._lib.bq_grad(self._h, _ptr(x), _ptr(y), pidx, B, float(scale),
@@ -180,7 +199,7 @@ class LSContext:
         for f in (u, w):
             if f.dtype != self.cdtype or tuple(f.shape) != (B, N, N, N) or not f.is_contiguous():
                 raise ValueError("u, w must be contiguous (B, N, N, N) tensors of the context's complex type")
-        g = torch.empty((N, N, N), dtype=self.rdtype, device=x.device) if out is None else out
+        g = self._out(out, (N, N, N))
         loss = ct.c_double(0.0)
         st = (L.SolveStats * B)()
         s = self._check(self._lib.bq_grad_ws(self._h, _ptr(x), _ptr(y), pidx, B, float(scale), _ptr(g),
@@ -260,8 +279,11 @@ class WProx:
             r = int(u.shape[0])
         else:
             raise ValueError("u must be an image or an (r,) + image-shape stack")
-        if P is not None and tuple(P.shape) != (3,) + self.shape:
-            raise ValueError("P must have shape (3,) + image shape")
+        if P is not None and (tuple(P.shape) != (3,) + self.shape or not P.is_contiguous()):
+            raise ValueError("P must be a contiguous tensor of shape (3,) + image shape")
+        if out is not None and (out.dtype != self.rdtype or out.device.type != "cuda"
+                                or tuple(out.shape) != self.shape or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous cuda image of the workspace's type")
         v = v.contiguous()
         u = None if u is None or r == 0 else u.contiguous()
         x = torch.empty_like(v) if out is None else out

@@ -40,11 +40,15 @@ enum { F_U = 0, F_W, F_R, F_RHAT, F_P, F_V, F_S, F_T };
 
 bq_status set_err(bq_ctx* c, bq_status s, const std::string& msg) {
   if (c) c->err = msg; else g_create_error = msg;
+  // a failed allocation leaves its error as the runtime's last error, which
+  // the next launch check (the library's or the caller's) would report
+  if (s == BQ_ENOMEM) (void)hipGetLastError();
   return s;
 }
 
 bq_status hip_err(bq_ctx* c, hipError_t e, const char* where) {
   std::string m = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();
   return set_err(c, BQ_EDEVICE, m);
 }
 
@@ -227,7 +231,8 @@ void det_adjoint(bq_ctx* c, int nb) {
 template <typename F>
 hipGraphExec_t iteration_graph(bq_ctx* c, int B, const void* x, const void* e, const void* inc, F&& iteration) {
   for (auto& g : c->graphs)
-    if (g.B == B && g.x == x && g.e == e && g.inc == inc) return g.exec;
+    if (g.B == B && g.x == x && g.e == e && g.inc == inc && g.xtile == c->plan_xtile && g.zf == c->plan_zf)
+      return g.exec;
   if (!c->gstream) {
     if (hipStreamCreate(&c->gstream) != hipSuccess) {
       c->gstream = nullptr;
@@ -260,7 +265,8 @@ hipGraphExec_t iteration_graph(bq_ctx* c, int B, const void* x, const void* e, c
     (void)hipGraphExecDestroy(c->graphs.front().exec);
     c->graphs.erase(c->graphs.begin());
   }
-  c->graphs.push_back({B, x, e, inc, exec});
+  c->graphs.push_back({B, x, e, inc, c->plan_xtile, c->plan_zf, exec});
+  ++c->graph_captures;
   return exec;
 }
 
@@ -301,7 +307,7 @@ bq_status bicgstab(bq_ctx* c, int B, const T* x, void* e, const C<double>* inc, 
   a.out2 = va.rhat;
   a.mask = RUN_ALL;
   if (green_apply<T>(a, c->stream, &c->timer)) return check_launch(c, "green_apply(init)");
-  sc_init(B, c->state, c->part_mv, c->np_mv, part_b, c->np_vec, bfix, c->g.tol, c->g.max_iter, c->stream);
+  sc_init(B, c->state, c->part_mv, c->np_mv, part_b, c->np_vec, bfix, c->g.tol, c->g.max_iter, c->brk, c->stream);
   if (warm) vec_zero_if_b0<T>(B, c->V, c->state, (C<T>*)e, c->stream);  // b = 0: the solution is 0
   // The scalar step that tests convergence and forms beta closes each pass
   // (and is issued once here for the first), so that a host check right
@@ -749,6 +755,9 @@ bq_status do_autotune(bq_ctx* c, int B_in, bq_tune_result* out) {
   c->plan_xtile = st == BQ_OK ? bx : 0;
   c->plan_zf = st == BQ_OK ? bz : 0;
   (void)hipStreamSynchronize(c->stream);
+  // graphs captured on the temporary potential are of no later use
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+  drop_graphs(c);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(x);
@@ -887,6 +896,24 @@ bq_status bq_set_plan(bq_ctx* c, int x_tile_rows, int zf_threads) {
     return set_err(c, BQ_EINVAL, "z-forward width not available for this grid and precision");
   c->plan_xtile = x_tile_rows;
   c->plan_zf = zf_threads;
+  return BQ_OK;
+}
+
+bq_status bq_set_breakdown_floor(bq_ctx* c, double floor) {
+  if (!c) return BQ_EINVAL;
+  if (!(floor >= 0) || !std::isfinite(floor)) return set_err(c, BQ_EINVAL, "floor must be finite and >= 0");
+  c->brk = floor;
+  return BQ_OK;
+}
+
+bq_status bq_get_info(const bq_ctx* c, bq_ctx_info* out) {
+  if (!c || !out) return BQ_EINVAL;
+  out->batch_capacity = c->Bcap;
+  out->x_tile_rows = c->plan_xtile;
+  out->zf_threads = c->plan_zf;
+  out->graphs_cached = (int)c->graphs.size();
+  out->graph_captures = c->graph_captures;
+  out->breakdown_floor = c->brk;
   return BQ_OK;
 }
 

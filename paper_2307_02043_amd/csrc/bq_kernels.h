@@ -115,7 +115,7 @@ template <typename T>
 void det_residual(int B, int N, C<T>* rdet, const C<T>* ymeas, double* partial, int np, hipStream_t st);
 
 void sc_init(int B, SysState* st, const double* part_r, int np_r, const double* part_b, int np_b,
-             double bnorm2_fixed, double tol, int max_iter, hipStream_t s);
+             double bnorm2_fixed, double tol, int max_iter, double brk, hipStream_t s);
 void sc_beta(int B, SysState* st, const double* part, int np, hipStream_t s);
 void sc_alpha(int B, SysState* st, const double* part, int np, hipStream_t s);
 void sc_s(int B, SysState* st, const double* part, int np, hipStream_t s);

@@ -449,6 +449,7 @@ bq_status bq_qn_create(bq_ctx* ls, bq_prox* px, const bq_qn_params* prm, const i
       (p.warm_start && (hipMalloc(&q->ufields, (size_t)total * q->V * q->csz) != hipSuccess ||
                         hipMalloc(&q->wfields, (size_t)total * q->V * q->csz) != hipSuccess))) {
     free_qn(q);
+    (void)hipGetLastError();  // not left for the next launch check to find
     g_qn_create_error = "out of memory";
     return BQ_ENOMEM;
   }

@@ -29,6 +29,7 @@ struct SysState {
   double tol;
   int max_iter;
   int mvs;                      // solver matvecs done (G applications)
+  double brk;                   // |rho|, |<rhat, v>| or |omega| below this: breakdown
 };
 
 // Which systems a solver pass works on.

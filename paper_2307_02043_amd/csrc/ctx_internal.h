@@ -47,22 +47,28 @@ struct bq_ctx {
   // launch shapes of the FFT passes (0: default), set by bq_autotune or
   // bq_set_plan; they change no value any call computes
   int plan_xtile = 0, plan_zf = 0;
+  // magnitude of rho, <rhat, v> or omega below which BiCGSTAB reports a
+  // breakdown (bq_set_breakdown_floor)
+  double brk = 1e-300;
   // systems per launch set (0: as many as the free device memory holds);
   // larger batches run as consecutive sub-batches
   int batch_limit = 0;
   // BQ_FLAG_GRAPH: one BiCGSTAB iteration of the batched path captured as a
-  // HIP graph per (batch size, potential, solution, incident table) and
-  // replayed on a stream of the library's own (a graph cannot be captured
-  // on the legacy null stream a caller may use), ordered after the caller's
-  // stream by an event.  Dropped whenever the batch buffers change.
+  // HIP graph per (batch size, potential, solution, incident table, launch
+  // shapes of the FFT passes) and replayed on a stream of the library's own
+  // (a graph cannot be captured on the legacy null stream a caller may use),
+  // ordered after the caller's stream by an event.  Dropped whenever the
+  // batch buffers change and after bq_autotune.
   struct IterGraph {
     int B;
     const void* x;
     const void* e;
     const void* inc;
+    int xtile, zf;  // plan_xtile / plan_zf the graph was captured under
     hipGraphExec_t exec;
   };
   std::vector<IterGraph> graphs;
+  long long graph_captures = 0;  // iteration graphs captured since creation
   hipStream_t gstream = nullptr;
   hipEvent_t gev = nullptr;
 };

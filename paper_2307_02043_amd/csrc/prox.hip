@@ -740,6 +740,7 @@ bq_status bq_prox_create(int nz, int ny, int nx, int precision, void* stream, bq
       hipMalloc((void**)&p->st, sizeof(ProxState)) != hipSuccess ||
       hipMalloc((void**)&p->rst, prox_rank_state_bytes()) != hipSuccess) {
     free_prox(p);
+    (void)hipGetLastError();  // not left for the next launch check to find
     g_prox_create_error = "out of device memory";
     return BQ_ENOMEM;
   }

@@ -161,7 +161,7 @@ __device__ inline bool finite3(double a, double b, double c) {
 
 __global__ void __launch_bounds__(256) k_sc_init(SysState* st, const double* part_r, int np_r,
                                                  const double* part_b, int np_b, double bfix,
-                                                 double tol, int max_iter) {
+                                                 double tol, int max_iter, double brk) {
   __shared__ double scratch[4 * 3];
   const int b = blockIdx.x;
   double rv[3], bv[1] = {bfix};
@@ -171,6 +171,7 @@ __global__ void __launch_bounds__(256) k_sc_init(SysState* st, const double* par
   SysState s{};
   s.tol = tol;
   s.max_iter = max_iter;
+  s.brk = brk;
   s.bnorm2 = bv[0];
   const double rn2 = rv[2];
   s.rho_x = rn2;  // rhat = r0, so <rhat, r0> = ||r0||^2
@@ -219,7 +220,7 @@ __global__ void __launch_bounds__(256) k_sc_beta(SysState* st, const double* par
       st[b] = s;
       return;
     }
-    if (hypot(s.omega_x, s.omega_y) < 1e-300) {
+    if (hypot(s.omega_x, s.omega_y) < s.brk) {
       s.status = SYS_BREAKDOWN;
       st[b] = s;
       return;
@@ -235,7 +236,7 @@ __global__ void __launch_bounds__(256) k_sc_beta(SysState* st, const double* par
     st[b] = s;
     return;
   }
-  if (hypot(rnx, rny) < 1e-300) {
+  if (hypot(rnx, rny) < s.brk) {
     s.status = SYS_BREAKDOWN;
     st[b] = s;
     return;
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(256) k_sc_alpha(SysState* st, const double* pa
   const double d = v[0] * v[0] + v[1] * v[1];
   if (!(isfinite(v[0]) && isfinite(v[1]))) {
     s.status = SYS_NONFINITE;
-  } else if (d == 0.0) {
+  } else if (d == 0.0 || hypot(v[0], v[1]) < s.brk) {
     s.status = SYS_BREAKDOWN;
   } else {
     const C<double> a = cmulc(C<double>{s.rhon_x, s.rhon_y}, C<double>{v[0], v[1]}) * (1.0 / d);
@@ -319,8 +320,9 @@ __global__ void __launch_bounds__(256) k_sc_omega(SysState* st, const double* pa
 }
 
 void sc_init(int B, SysState* st, const double* part_r, int np_r, const double* part_b, int np_b,
-             double bfix, double tol, int max_iter, hipStream_t s) {
-  hipLaunchKernelGGL(k_sc_init, dim3(B), dim3(256), 0, s, st, part_r, np_r, part_b, np_b, bfix, tol, max_iter);
+             double bfix, double tol, int max_iter, double brk, hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_init, dim3(B), dim3(256), 0, s, st, part_r, np_r, part_b, np_b, bfix, tol, max_iter,
+                     brk);
 }
 void sc_beta(int B, SysState* st, const double* part, int np, hipStream_t s) {
   hipLaunchKernelGGL(k_sc_beta, dim3(B), dim3(256), 0, s, st, part, np);

@@ -440,3 +440,45 @@ def test_sub_batches_equal_one_launch_set(dev, prec, model):
     with pytest.raises(BQError):
         ctx.set_batch_limit(-1)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graphs_follow_the_launch_plan(dev, prec):
+    """Replayed iteration graphs are keyed on the launch shapes: after
+    bq_set_plan the next solve captures its graphs again (a cached graph of
+    the old shapes is not replayed), going back to cached shapes captures
+    nothing, bq_autotune drops the graphs, and the gradient stays the same
+    bit for bit throughout."""
+    from paper_2307_02043_amd import BQError
+    x, y, dirs, idx, _, _ = _c1_reference()
+    N = x.shape[0]
+    rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    ctx = _ctx(N, dirs, prec, tol=1e-13 if prec == "f64" else 1e-6, max_iter=400, graphs=True)
+    xt, yt = torch.from_numpy(x).to(dev, rd), torch.from_numpy(y).to(dev, cd)
+    g0, f0, _ = ctx.grad(xt, yt, idx, 0.25)
+    n0 = ctx.info()["graph_captures"]
+    assert n0 >= 1
+    g, f, _ = ctx.grad(xt, yt, idx, 0.25)
+    assert torch.equal(g, g0) and ctx.info()["graph_captures"] == n0
+    other = None
+    for xr, zt in ((8, 0), (16, 0), (32, 0), (0, 256), (0, 1024)):
+        try:
+            ctx.set_plan(xr, zt)
+        except BQError:
+            continue
+        other = (xr, zt)
+        break
+    assert other is not None
+    g, f, _ = ctx.grad(xt, yt, idx, 0.25)
+    info = ctx.info()
+    assert (info["x_tile_rows"], info["zf_threads"]) == other
+    assert info["graph_captures"] == 2 * n0
+    assert torch.equal(g, g0) and f == f0
+    ctx.set_plan(0, 0)
+    g, f, _ = ctx.grad(xt, yt, idx, 0.25)
+    assert ctx.info()["graph_captures"] == 2 * n0 and torch.equal(g, g0)
+    ctx.autotune(len(idx))
+    assert ctx.info()["graphs_cached"] == 0
+    g, f, _ = ctx.grad(xt, yt, idx, 0.25)
+    assert torch.equal(g, g0) and f == f0
+    ctx.close()

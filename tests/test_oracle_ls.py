@@ -262,3 +262,28 @@ def test_incident_field_is_the_plane_wave_of_the_background(N):
     # a corner voxel sits at r = -(N-1)/2 h on every axis
     corner = np.exp(-1j * kb * (N - 1) / 2 * h * d.sum())
     assert abs(u[0, 0, 0] - corner) < 1e-12
+
+
+def test_breakdown_floor_stops_where_an_iteration_cap_would():
+    """BiCGSTAB with a breakdown floor stops at the first |rho| below it;
+    its iterate is then the one a run capped at that many iterations
+    returns, and a floor above every scalar stops before the first
+    iteration with the starting point."""
+    N = 12
+    geom = _geom(N)
+    model = lsmodel.LSModel(geom)
+    x = _phantom(N, 5)
+    d = syn.illumination_directions(1, 35.0, np.random.default_rng(2))[0]
+    uin = lsmodel.incident_field(geom, d)
+    u, it, st, _ = model.solve_forward(x, uin, 1e-15, 50, breakdown=1e300)
+    assert st == lsmodel.BREAKDOWN and it == 0 and np.array_equal(u, uin)
+    # |rho_k| = |<rhat, r_{k-1}>| falls geometrically with k, so each floor
+    # is crossed after some iterations, later for a lower floor
+    ref_it = None
+    for floor in (1e-2, 1e-4, 1e-6):
+        u, it, st, _ = model.solve_forward(x, uin, 0.0, 40, breakdown=floor)
+        assert st == lsmodel.BREAKDOWN and 0 < it < 40
+        uc, itc, stc, _ = model.solve_forward(x, uin, 0.0, it)
+        assert itc == it and stc == lsmodel.NOT_CONVERGED and np.array_equal(u, uc)
+        assert ref_it is None or it >= ref_it
+        ref_it = it
