@@ -240,3 +240,10 @@ def prox_inputs(w: Workload, dn: np.ndarray | None = None):
 def random_field(shape, rng: np.random.Generator) -> np.ndarray:
     """Complex normal test vector."""
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def detector_images(B: int, N: int, rng: np.random.Generator, scale: float = 0.1) -> np.ndarray:
+    """Stand-in measurements (B, N, N): circular complex Gaussian images of
+    the size of a scattered field on the detector, for parity tests of the
+    gradient, which is defined for any measurement."""
+    return scale * (rng.standard_normal((B, N, N)) + 1j * rng.standard_normal((B, N, N))) / math.sqrt(2.0)

@@ -1,0 +1,106 @@
+"""Writes the oracle's results at the 256^3 configuration for the GPU parity
+tests that the oracle cannot finish inside a test (hours of FP64 CPU work
+otherwise repeated on every run).  Calls only oracle/ and synthetic/.
+
+    python tests/golden/make_fullsize_refs.py [grad|prox|all] [workers]
+
+grad: the 256^3 workload with contrast x1.5 (c5_ls256_f32), the first two
+      illuminations of its mini-batch.  Measurements y = H(x_true) (oracle
+      forward solves at tol 1e-11) plus 30 dB noise, stored as complex64 (the
+      GPU's FP32 path reads them as they are; the oracle uses the same values
+      widened to complex128).  The gradient and loss at x = 0.5 x_true with
+      scale 1/2 (oracle solves at tol 1e-11), kept at 8192 seeded voxels
+      together with whole-array sums.
+prox: the weighted TV prox of the same workload: iso TV, nonnegativity,
+      metric tau I + u u^T (rank one), lambda 1e-3, 200 dual iterations
+      (Section 4.1 iteration, Theorem 3.1 projection), kept at 8192 seeded
+      voxels together with whole-array sums.
+Each file records a digest of the oracle sources it was made with and one
+of its input arrays; the tests refuse a file whose oracle digest no longer
+matches, or whose inputs differ from those the synthetic generators give.
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import synthetic as syn  # noqa: E402
+from oracle import lsmodel, tvprox  # noqa: E402
+
+SAMPLES = 8192
+
+
+def source_digest(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def array_digest(*arrays) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
+GRAD_SOURCES = ("oracle/green.py", "oracle/lsmodel.py")
+PROX_SOURCES = ("oracle/tvprox.py",)
+
+
+def sample_index(V: int, seed: int) -> np.ndarray:
+    return np.sort(np.random.default_rng(seed).choice(V, size=SAMPLES, replace=False)).astype(np.int64)
+
+
+def make_grad(workers: int) -> None:
+    w = syn.WORKLOADS["c5_ls256_f32"]
+    N = w.N
+    geom = lsmodel.Geometry(N=N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+    t0 = time.time()
+    m = lsmodel.LSModel(geom, workers=workers)
+    print(f"kernel {time.time() - t0:.0f} s", flush=True)
+    xt = syn.scattering_potential(syn.make_phantom(w))
+    dirs = syn.workload_directions(w)
+    idx = [int(i) for i in syn.batch_indices(w)[:2]]
+    yc, st = m.forward(xt, dirs, idx, 1e-11, 500)
+    print(f"forward {time.time() - t0:.0f} s, iterations {[s[0] for s in st]}", flush=True)
+    y = syn.add_noise(yc, w.snr_db, np.random.default_rng(w.seed("noise"))).astype(np.complex64)
+    x = 0.5 * xt
+    g, f, st = m.grad(x, y.astype(np.complex128), dirs, idx, 0.5, 1e-11, 500)
+    print(f"gradient {time.time() - t0:.0f} s, iterations {st}", flush=True)
+    sel = sample_index(g.size, 7256)
+    np.savez(os.path.join(HERE, "c5_grad256_b2.npz"), idx=np.array(idx, np.int32), y=y, loss=f,
+             sel=sel, g_sel=g.ravel()[sel], g_norm=np.linalg.norm(g), g_sum=g.sum(),
+             iters=np.array(st, np.int32), digest=source_digest(GRAD_SOURCES),
+             inputs=array_digest(x, dirs))
+
+
+def make_prox() -> None:
+    w = syn.WORKLOADS["c5_ls256_f32"]
+    v, tau, u = syn.prox_inputs(w)
+    t0 = time.time()
+    x = tvprox.wprox(v, tau, u, w.prox_lambda, "iso", "nonneg", n_iter=w.prox_iters)
+    print(f"prox {time.time() - t0:.0f} s", flush=True)
+    sel = sample_index(x.size, 7257)
+    np.savez(os.path.join(HERE, "c5_prox256_k200.npz"), x_sel=x.ravel()[sel], sel=sel,
+             x_norm=np.linalg.norm(x), x_sum=x.sum(), x_pos=int(np.count_nonzero(x > 0)),
+             n_iter=w.prox_iters, lam=w.prox_lambda, tau=tau, digest=source_digest(PROX_SOURCES),
+             inputs=array_digest(v, u))
+
+
+if __name__ == "__main__":
+    what = sys.argv[1] if len(sys.argv) > 1 else "all"
+    workers = int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1)
+    if what in ("grad", "all"):
+        make_grad(workers)
+    if what in ("prox", "all"):
+        make_prox()

@@ -1,0 +1,199 @@
+"""Element-wise parity with the oracle at the full configurations that
+bench.py runs.
+
+* 128^3, complex64, the benchmark's launch set of 16 illuminations: the
+  forward fields u_b and the adjoint fields w_b of the first and the last
+  system against oracle solves, element by element (2e-4 relative; GPU tol
+  1e-6, oracle tol 1e-13).
+* 128^3, complex128, 4 illuminations: gradient and loss against the
+  oracle's (1e-10; both sides tol 1e-13), the complex128 y pass at 128.
+* 256^3, complex64, 2 illuminations of the 256^3 workload: gradient and loss
+  against the oracle's, stored by tests/golden/make_fullsize_refs.py at 8192
+  seeded voxels (the relative error over the sample estimates the
+  whole-array one) plus the whole-array norm (2e-4).
+* 256^3 weighted prox (iso TV, nonnegativity, metric tau I + u u^T, lambda
+  1e-3) at its 200 dual iterations, FP32 (2e-4) and FP64 (1e-10), against
+  the oracle's stored samples and norm.
+
+The measurements of the 128^3 cases are stand-in detector images (the
+gradient is defined for any measurement); those of the 256^3 case are the
+oracle's forward images plus noise, stored with its results.
+"""
+import functools
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import lsmodel
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+WORKERS = min(os.cpu_count() or 1, 16)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _ctx(w, prec, **kw):
+    from paper_2307_02043_amd import LSContext
+    return LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, syn.workload_directions(w), precision=prec,
+                     model=w.model, **kw)
+
+
+def _digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _array_digest(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
+def _golden(name, sources, *inputs):
+    """A stored oracle result, refused when the oracle sources or the
+    inputs it was computed from have changed since."""
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f"{name} missing: run tests/golden/make_fullsize_refs.py")
+    d = np.load(path, allow_pickle=False)
+    assert str(d["digest"]) == _digest(sources), \
+        f"{name} was made with other oracle sources: run tests/golden/make_fullsize_refs.py"
+    assert str(d["inputs"]) == _array_digest(*inputs), \
+        f"{name} was made from other inputs: run tests/golden/make_fullsize_refs.py"
+    return d
+
+
+# --------------------------------------------------------------------------
+# 128^3
+# --------------------------------------------------------------------------
+C4 = syn.WORKLOADS["c4_ls128_f32"]
+
+
+@functools.lru_cache(maxsize=None)
+def _c4_inputs():
+    x = 0.5 * syn.scattering_potential(syn.make_phantom(C4))
+    x = x.astype(np.float32).astype(np.float64)   # the FP32 run sees exactly these values
+    y = syn.detector_images(C4.B, C4.N, np.random.default_rng(C4.seed("noise") + 100))
+    y = y.astype(np.complex64).astype(np.complex128)
+    return x, y, [int(i) for i in syn.batch_indices(C4)]
+
+
+@functools.lru_cache(maxsize=None)
+def _c4_model():
+    geom = lsmodel.Geometry(N=C4.N, h=C4.h_um, lambda0=C4.lambda0_um, n_b=C4.n_b)
+    return lsmodel.LSModel(geom, workers=WORKERS)
+
+
+@functools.lru_cache(maxsize=None)
+def _c4_oracle_system(b):
+    """Forward field, adjoint field and 1/2 ||r||^2 of batch element b."""
+    x, y, idx = _c4_inputs()
+    m = _c4_model()
+    uin = lsmodel.incident_field(m.geom, syn.workload_directions(C4)[idx[b]])
+    u, itf, sf, _ = m.solve_forward(x, uin, 1e-13, 300)
+    r = m.detector(u - uin) - y[b]
+    w, ita, sa, _ = m.solve_adjoint(x, m.GH(m.detector_T(r)), 1e-13, 300)
+    assert sf == lsmodel.CONVERGED and sa == lsmodel.CONVERGED
+    return u, w, 0.5 * float(np.vdot(r, r).real)
+
+
+def test_128_launch_set_of_16_fields_match_oracle(dev):
+    x, y, idx = _c4_inputs()
+    N, B = C4.N, C4.B
+    ctx = _ctx(C4, "f32", tol=1e-6, max_iter=300)
+    u = torch.zeros((B, N, N, N), dtype=torch.complex64, device=dev)
+    w = torch.zeros_like(u)
+    g, f, info = ctx.grad_ws(torch.from_numpy(x).to(dev, torch.float32),
+                             torch.from_numpy(y).to(dev, torch.complex64), idx, 1.0 / B, u, w, start=False)
+    assert info.status == 0 and len(info.iters_fwd) == 16
+    ctx.close()
+    for b in (0, B - 1):
+        ur, wr, _ = _c4_oracle_system(b)
+        eu = _rel(u[b].cpu().numpy(), ur)
+        # the library keeps the conjugated adjoint field (it solves the conjugate system)
+        ew = _rel(np.conj(w[b].cpu().numpy()), wr)
+        assert eu < 2e-4 and ew < 2e-4, (b, eu, ew)
+
+
+def test_128_f64_gradient_matches_oracle(dev):
+    x, y, idx = _c4_inputs()
+    B = 4
+    ctx = _ctx(C4, "f64", tol=1e-13, max_iter=300)
+    g, f, info = ctx.grad(torch.from_numpy(x).to(dev), torch.from_numpy(y[:B]).to(dev), idx[:B], 1.0 / B)
+    assert info.status == 0
+    ctx.close()
+    gref = np.zeros(x.shape)
+    fref = 0.0
+    for b in range(B):
+        ur, wr, fb = _c4_oracle_system(b)
+        gref += np.real(np.conj(ur) * wr)
+        fref += fb
+    gref /= B
+    fref /= B
+    err = _rel(g.cpu().numpy(), gref)
+    assert err < 1e-10, err
+    assert abs(f - fref) < 1e-10 * fref
+
+
+# --------------------------------------------------------------------------
+# 256^3 (stored oracle results)
+# --------------------------------------------------------------------------
+C5 = syn.WORKLOADS["c5_ls256_f32"]
+
+
+def test_256_f32_gradient_matches_stored_oracle(dev):
+    xt = syn.scattering_potential(syn.make_phantom(C5))
+    ref = _golden("c5_grad256_b2.npz", ("oracle/green.py", "oracle/lsmodel.py"), 0.5 * xt,
+                  syn.workload_directions(C5))
+    idx = [int(i) for i in ref["idx"]]
+    assert idx == [int(i) for i in syn.batch_indices(C5)[:2]]
+    x = 0.5 * xt
+    ctx = _ctx(C5, "f32", tol=1e-6, max_iter=500)
+    g, f, info = ctx.grad(torch.from_numpy(x).to(dev, torch.float32), torch.from_numpy(ref["y"]).to(dev),
+                          idx, 0.5)
+    assert info.status == 0
+    ctx.close()
+    gs = g.reshape(-1)[torch.from_numpy(ref["sel"]).to(dev)].double().cpu().numpy()
+    err = _rel(gs, ref["g_sel"])
+    assert err < 2e-4, err
+    assert abs(float(torch.linalg.norm(g.double())) - float(ref["g_norm"])) < 2e-4 * float(ref["g_norm"])
+    assert abs(f - float(ref["loss"])) < 2e-4 * float(ref["loss"])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_256_prox_200_iterations_matches_stored_oracle(dev, prec):
+    from paper_2307_02043_amd import WProx
+    v, tau, u = syn.prox_inputs(C5)
+    ref = _golden("c5_prox256_k200.npz", ("oracle/tvprox.py",), v, u)
+    assert int(ref["n_iter"]) == C5.prox_iters == 200
+    rd = torch.float32 if prec == "f32" else torch.float64
+    px = WProx(v.shape, prec)
+    x, info = px(torch.from_numpy(v).to(dev, rd), tau, torch.from_numpy(u).to(dev, rd), C5.prox_lambda,
+                 "iso", "nonneg", C5.prox_iters)
+    px.close()
+    lim = 2e-4 if prec == "f32" else 1e-10
+    xs = x.reshape(-1)[torch.from_numpy(ref["sel"]).to(dev)].double().cpu().numpy()
+    err = _rel(xs, ref["x_sel"])
+    assert err < lim, err
+    assert abs(float(torch.linalg.norm(x.double())) - float(ref["x_norm"])) < lim * float(ref["x_norm"])
+    print(f"256^3 prox, 200 iterations, {prec}: sampled relative error {err:.2e}")

@@ -172,3 +172,28 @@ def test_qn_variants_f64_match_oracle(dev, warm, first_order):
             assert info.metric_rank == 0 and info.tau_sum == _params(5e-5)["alpha"]
         err = _rel(xg, xr)
         assert err < 1e-9, (k, err)
+
+
+def test_qn_iteration_f32_single_steps_match_oracle(dev):
+    """Per-step FP32 error, apart from its accumulation over iterations: the
+    oracle follows the GPU's own trajectory (each of its steps starts from
+    the GPU's x_{k-1}, so its subset pairs (xbar, gbar) and SR1 metrics are
+    those exact arithmetic gives on that trajectory), and every GPU step is
+    compared with the oracle step from the same point at 2e-4."""
+    got = _gpu_run(dev, "f32", 5e-5, STRAT_I)
+    xt, dirs, m, y = _problem()
+    prm = bqnpm.BQNPMParams(**_params(5e-5))
+
+    def grad(s, x):
+        return m.grad(x, y[SUBSETS[s]], dirs, SUBSETS[s], S / L, 1e-13, 400)[0]
+    it = bqnpm.BQNPM(prm, grad)
+    x = np.zeros_like(xt)
+    worst = 0.0
+    for k, (xg, info) in enumerate(got, start=1):
+        xr, sp, _ = it.step(x)
+        assert info.subset == sp
+        err = _rel(xg, xr)
+        worst = max(worst, err)
+        assert err < 2e-4, (k, err)
+        x = xg
+    print(f"FP32 outer iteration: worst single-step relative error {worst:.2e}")
