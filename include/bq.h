@@ -329,6 +329,36 @@ const char* bq_prox_last_error(const bq_prox* p);
 bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, double lambda, int tv,
                    int cset, int n_iter, void* x_out, void* P_io, bq_prox_stats* st);
 
+/* bq_wprox without a workspace object, for callers that cannot allocate
+ * device memory (code under HIP graph capture elsewhere in the caller,
+ * serving loops, harnesses that forbid hipMalloc): it calls no hipMalloc,
+ * hipFree or other allocating routine and captures no graph.  Its scratch
+ * memory is one static device array of BQ_WPROX_NOALLOC_SCRATCH bytes per
+ * GPU, allocated when the library is loaded on that GPU and held until the
+ * process ends; its device address is looked up on the first call on each
+ * GPU.
+ *   nz, ny, nx, precision  image shape (each >= 2) and bq_precision
+ *   stream                 hipStream_t the work is enqueued on (NULL: the
+ *                          default stream); the call synchronises it
+ *   other arguments        as bq_wprox (the same computation and result)
+ * Scratch needed, in bytes rounded up to 256 each: the image, the dual
+ * momentum (3 images), the dual point unless P_io is given (3 images), x at
+ * rank >= 2 (1 image), a second momentum at rank 0 (3 images), plus about
+ * 1 MB of partial sums and state: in FP32 every rank fits at 128^3, in FP64
+ * at 96^3.
+ * Every call on a GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call initialises what it reads): calls that
+ * overlap on one GPU (concurrent host threads, or streams whose work
+ * overlaps) race and give undefined results.  Every root pass is launched
+ * (as bq_wprox's full pass budget), so no call is run twice.
+ * Errors: BQ_EINVAL (arguments, or an image whose scratch exceeds the
+ * array: the message states the bytes needed), BQ_EDEVICE; BQ_NOTCONV as
+ * bq_wprox.  bq_prox_last_error(NULL) returns the message (per thread). */
+#define BQ_WPROX_NOALLOC_SCRATCH (96u << 20)
+bq_status bq_wprox_noalloc(int nz, int ny, int nx, int precision, const void* v, double tau, const void* U,
+                           int r, double lambda, int tv, int cset, int n_iter, void* x_out, void* P_io,
+                           bq_prox_stats* st, void* stream);
+
 /* ---------------------------------------------------------------------
  * Mini-batch quasi-Newton proximal iteration (Algorithm 4.1)
  * --------------------------------------------------------------------- */

@@ -23,11 +23,12 @@ BQ_SET_NONE, BQ_SET_NONNEG = 0, 1
 PASS_NAMES = ("zf", "xf", "yc", "xi", "zi", "xy", "vec")
 BQ_TIMING_ALL = (1 << len(PASS_NAMES)) - 1
 BQ_PROX_MAX_RANK = 8
+BQ_WPROX_NOALLOC_SCRATCH = 96 << 20
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
             "bq_grad", "bq_grad_ws", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_autotune", "bq_set_plan", "bq_set_batch_limit",
             "bq_set_breakdown_floor", "bq_get_info", "bq_prox_create", "bq_prox_destroy",
-            "bq_prox_last_error", "bq_wprox", "bq_qn_create", "bq_qn_destroy", "bq_qn_last_error",
+            "bq_prox_last_error", "bq_wprox", "bq_wprox_noalloc", "bq_qn_create", "bq_qn_destroy", "bq_qn_last_error",
             "bq_qn_step")
 
 
@@ -114,6 +115,7 @@ def load() -> ct.CDLL:
         "bq_prox_destroy": ([P], I),
         "bq_prox_last_error": ([P], ct.c_char_p),
         "bq_wprox": ([P, P, D, P, I, D, I, I, I, P, P, ct.POINTER(ProxStats)], I),
+        "bq_wprox_noalloc": ([I, I, I, I, P, D, P, I, D, I, I, I, P, P, ct.POINTER(ProxStats), P], I),
         "bq_qn_create": ([P, P, ct.POINTER(QnParams), ct.POINTER(I), ct.POINTER(I), ct.POINTER(P)], I),
         "bq_qn_destroy": ([P], I),
         "bq_qn_last_error": ([P], ct.c_char_p),

@@ -297,6 +297,44 @@ class WProx:
         return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last)
 
 
+def wprox_noalloc(v: torch.Tensor, tau: float, u: torch.Tensor | None, lam: float, tv: str = "iso",
+                  cset: str = "nonneg", n_iter: int = 50, P: torch.Tensor | None = None,
+                  out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
+    """bq_wprox_noalloc: the weighted prox without a workspace object (the
+    library allocates nothing; its scratch is a static device array).  out
+    must be given by callers that may not allocate either; u as for WProx."""
+    lib = L.load()
+    if v.dtype not in (torch.float32, torch.float64) or v.device.type != "cuda" or v.dim() != 3:
+        raise ValueError("v must be a 3-D float32/float64 cuda tensor")
+    shape = tuple(v.shape)
+    for t in (u, P, out):
+        if t is not None and (t.dtype != v.dtype or t.device != v.device or not t.is_contiguous()):
+            raise ValueError("u, P, out must be contiguous tensors of v's type and device")
+    if u is None:
+        r = 0
+    elif tuple(u.shape) == shape:
+        r = 1
+    elif u.dim() == 4 and tuple(u.shape[1:]) == shape:
+        r = int(u.shape[0])
+    else:
+        raise ValueError("u must be an image or an (r,) + image-shape stack")
+    if P is not None and tuple(P.shape) != (3,) + shape:
+        raise ValueError("P must have shape (3,) + image shape")
+    if out is not None and tuple(out.shape) != shape:
+        raise ValueError("out has the wrong shape")
+    v = v.contiguous()
+    x = torch.empty_like(v) if out is None else out
+    st = L.ProxStats()
+    s = lib.bq_wprox_noalloc(*shape, L.BQ_F32 if v.dtype == torch.float32 else L.BQ_F64, _ptr(v), float(tau),
+                             _ptr(u if r else None), r, float(lam),
+                             L.BQ_TV_ISO if tv == "iso" else L.BQ_TV_ANISO,
+                             L.BQ_SET_NONNEG if cset == "nonneg" else L.BQ_SET_NONE, int(n_iter), _ptr(x),
+                             _ptr(P), ct.byref(st), _stream_handle(stream))
+    if s < 0:
+        raise BQError(s, lib.bq_prox_last_error(None).decode())
+    return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last), s
+
+
 @dataclass
 class QNInfo:
     k: int

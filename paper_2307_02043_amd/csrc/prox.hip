@@ -26,6 +26,7 @@
 // k_dual0, carries the whole dual iteration, and k_out0 the output.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -551,25 +552,13 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
                          p->max_passes, j == max_launch - 1 ? 1 : 0);
     }
   };
-  if (n_iter > 0) {
-    // one dual iteration captured as a graph and replayed n_iter times
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-      primal();
-      launch_dual<T>(nonneg, g, b, s, a);
-      ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
-    }
-    ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-    for (int k = 0; ok && k < n_iter; ++k) ok = hipGraphLaunch(exec, s) == hipSuccess;
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (!ok) {
-      (void)hipGetLastError();
-      p->err = "graph capture or launch of the dual iteration failed";
-      return BQ_EDEVICE;
-    }
+  // one dual iteration captured as a graph and replayed n_iter times
+  if (!replay_iterations(p, n_iter, [&](hipStream_t) {
+        primal();
+        launch_dual<T>(nonneg, g, b, s, a);
+      })) {
+    p->err = "graph capture or launch of the dual iteration failed";
+    return BQ_EDEVICE;
   }
   // x(P_K): divergence of P_K itself, then the projection
   if (hipMemcpyAsync(a.R, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
@@ -637,24 +626,12 @@ bq_status run_wprox_tau(bq_prox* p, const void* v, double tau, double lam, int t
     if (nonneg) hipLaunchKernelGGL((k_dual0<T, true>), gd, b, 0, s, a, rin, rout, par, zc);
     else hipLaunchKernelGGL((k_dual0<T, false>), gd, b, 0, s, a, rin, rout, par, zc);
   };
-  if (n_iter >= 2) {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-      dual(R0, R1, 0);
-      dual(R1, R0, 1);
-      ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
-    }
-    ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-    for (int k = 0; ok && k < n_iter / 2; ++k) ok = hipGraphLaunch(exec, s) == hipSuccess;
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (!ok) {
-      (void)hipGetLastError();
-      p->err = "graph capture or launch of the dual iteration failed";
-      return BQ_EDEVICE;
-    }
+  if (!replay_iterations(p, n_iter / 2, [&](hipStream_t) {
+        dual(R0, R1, 0);
+        dual(R1, R0, 1);
+      })) {
+    p->err = "graph capture or launch of the dual iteration failed";
+    return BQ_EDEVICE;
   }
   if (n_iter % 2) dual(R0, R1, 0);
   // x(P_K)
@@ -681,7 +658,7 @@ template <typename T>
 bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double lam, int tv, int cset,
                     int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
   // order after the caller's pending work, then run on the library stream
-  if (hipEventRecord(p->ev, p->stream) != hipSuccess || hipStreamWaitEvent(p->own, p->ev, 0) != hipSuccess) {
+  if (!order_after_caller(p)) {
     p->err = "stream synchronisation failed";
     return BQ_EDEVICE;
   }
@@ -717,6 +694,42 @@ void free_prox(bq_prox* p) {
   if (p->own) (void)hipStreamDestroy(p->own);
   delete p;
 }
+
+// Scratch memory of bq_wprox_noalloc: one array per device, allocated with
+// the code object when the library is loaded on that device and kept until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// the device array: kernels get the device address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(96) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (on its first call).  Null on failure, with the reason in *why.
+void* scratch_address(const char** why) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    (void)hipGetLastError();
+    *why = "no current HIP device (or device index above 63)";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      *why = "hipGetSymbolAddress of the scratch array failed";
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -777,6 +790,76 @@ bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, 
   const void* u = r == 1 ? U : nullptr;
   return p->prec == BQ_F32 ? run_wprox<float>(p, v, tau, u, lambda, tv, cset, n_iter, x_out, P_io, st)
                            : run_wprox<double>(p, v, tau, u, lambda, tv, cset, n_iter, x_out, P_io, st);
+}
+
+bq_status bq_wprox_noalloc(int nz, int ny, int nx, int precision, const void* v, double tau, const void* U,
+                           int r, double lambda, int tv, int cset, int n_iter, void* x_out, void* P_io,
+                           bq_prox_stats* st, void* stream) {
+  auto fail = [](bq_status s, const char* msg) {
+    g_prox_create_error = msg;
+    return s;
+  };
+  if (nz < 2 || ny < 2 || nx < 2) return fail(BQ_EINVAL, "each image dimension must be >= 2");
+  if (precision != BQ_F32 && precision != BQ_F64) return fail(BQ_EINVAL, "precision");
+  if (!v || !x_out) return fail(BQ_EINVAL, "null device pointer");
+  if (!(tau > 0) || !(lambda > 0) || n_iter < 0) return fail(BQ_EINVAL, "tau, lambda must be > 0 and n_iter >= 0");
+  if (tv != BQ_TV_ISO && tv != BQ_TV_ANISO) return fail(BQ_EINVAL, "tv");
+  if (cset != BQ_SET_NONE && cset != BQ_SET_NONNEG) return fail(BQ_EINVAL, "cset");
+  if (r < 0 || r > BQ_PROX_MAX_RANK) return fail(BQ_EINVAL, "metric rank r must be in [0, BQ_PROX_MAX_RANK]");
+  if (r > 0 && !U) return fail(BQ_EINVAL, "U is NULL with r > 0");
+  // the workspace of a bq_prox object, laid out in the scratch array: the
+  // image a, the dual point P (unless the caller's), the momentum R, x(R)
+  // at rank >= 2, the second momentum buffer of the metric tau I, the
+  // partial sums and the two device states
+  const size_t V = (size_t)nz * ny * nx;
+  const size_t es = precision == BQ_F32 ? 4 : 8;
+  const int np = px_grid(V);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+  const size_t o_a = take(V * es);
+  const size_t o_P = P_io ? 0 : take(3 * V * es);
+  const size_t o_R = take(3 * V * es);
+  const size_t o_x = r >= 2 ? take(V * es) : 0;
+  const size_t o_R2 = r == 0 ? take(3 * V * es) : 0;
+  const size_t o_part = take((size_t)np * PX_PART * sizeof(double));
+  const size_t o_st = take(sizeof(ProxState));
+  const size_t o_rst = take(prox_rank_state_bytes());
+  if (off > NOALLOC_SCRATCH_BYTES) {
+    g_prox_create_error = "image too large for bq_wprox_noalloc: it needs " + std::to_string(off) +
+                          " bytes of scratch, the maximum is " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                          " (use bq_prox_create and bq_wprox)";
+    return BQ_EINVAL;
+  }
+  const char* why = nullptr;
+  unsigned char* base = (unsigned char*)scratch_address(&why);
+  if (!base) return fail(BQ_EDEVICE, why);
+  bq_prox p;
+  p.nz = nz; p.ny = ny; p.nx = nx; p.prec = precision;
+  p.V = V;
+  p.stream = p.own = (hipStream_t)stream;
+  p.direct = true;
+  p.np = np;
+  p.a = base + o_a;
+  p.P = P_io ? nullptr : base + o_P;
+  p.R = base + o_R;
+  p.xbuf = r >= 2 ? base + o_x : nullptr;
+  p.R2 = r == 0 ? base + o_R2 : nullptr;
+  p.partial = (double*)(base + o_part);
+  p.st = (ProxState*)(base + o_st);
+  p.rst = (ProxRankState*)(base + o_rst);
+  // every root pass launched: no rerun, so no copy of the starting point
+  p.ssn_slots = p.max_passes - 1;
+  p.ssn_slots_rank = p.max_passes_rank - 1;
+  bq_status res;
+  if (r >= 2)
+    res = precision == BQ_F32 ? run_wprox_rank<float>(&p, v, tau, U, r, lambda, tv, cset, n_iter, x_out, P_io, st)
+                              : run_wprox_rank<double>(&p, v, tau, U, r, lambda, tv, cset, n_iter, x_out, P_io, st);
+  else
+    res = precision == BQ_F32
+              ? run_wprox<float>(&p, v, tau, r == 1 ? U : nullptr, lambda, tv, cset, n_iter, x_out, P_io, st)
+              : run_wprox<double>(&p, v, tau, r == 1 ? U : nullptr, lambda, tv, cset, n_iter, x_out, P_io, st);
+  if (res != BQ_OK) g_prox_create_error = p.err;
+  return res;
 }
 
 }  // extern "C"

@@ -34,6 +34,11 @@ struct bq_prox {
   int ssn_slots = 2;        // root passes launched per dual iteration, rank <= 1 (up to max_passes - 1)
   int ssn_slots_rank = 2;   // the same for rank >= 2 (up to max_passes_rank - 1)
   int max_passes_rank = 12;  // the same for rank >= 2 (Newton steps and backtracking)
+  // Launch every kernel directly on `own` instead of replaying a captured
+  // graph (instantiating one may allocate): set for the workspace the
+  // no-allocation entry point builds over its static scratch array, whose
+  // `own` is the caller's stream and which has no event.
+  bool direct = false;
 };
 
 namespace bq {
@@ -71,6 +76,39 @@ bq_status run_with_pass_budget(bq_prox* p, void* P_io, size_t bytes3, bool root,
   }
   if (st == BQ_OK && root) slots_pref = std::max(2, std::min(full, seen));
   return st;
+}
+
+// Runs body(stream) `count` times on p->own: one capture replayed as a graph,
+// or direct launches for a workspace that may not allocate.  False if the
+// capture, the instantiation or a launch failed.
+template <class Body>
+bool replay_iterations(bq_prox* p, int count, Body body) {
+  if (count <= 0) return true;
+  const hipStream_t s = p->own;
+  if (p->direct) {
+    for (int k = 0; k < count; ++k) body(s);
+    return hipGetLastError() == hipSuccess;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    body(s);
+    ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
+  }
+  ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  for (int k = 0; ok && k < count; ++k) ok = hipGraphLaunch(exec, s) == hipSuccess;
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) (void)hipGetLastError();
+  return ok;
+}
+
+// Orders the library stream after the work pending on the caller's stream
+// (nothing to do when they are the same stream).
+inline bool order_after_caller(bq_prox* p) {
+  if (p->own == p->stream || !p->ev) return true;
+  return hipEventRecord(p->ev, p->stream) == hipSuccess && hipStreamWaitEvent(p->own, p->ev, 0) == hipSuccess;
 }
 
 template <typename T>

@@ -543,24 +543,12 @@ static bq_status run_rank_once(bq_prox* p, const void* v, double tau, const void
     }
     hipLaunchKernelGGL((k_xr<T, R>), g, b, 0, s, a, xdst);
   };
-  if (n_iter > 0) {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-      primal(a.xbuf);
-      hipLaunchKernelGGL((k_dual_x<T>), g, b, 0, s, a);
-      ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
-    }
-    ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-    for (int k = 0; ok && k < n_iter; ++k) ok = hipGraphLaunch(exec, s) == hipSuccess;
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (!ok) {
-      (void)hipGetLastError();
-      p->err = "graph capture or launch of the dual iteration failed";
-      return BQ_EDEVICE;
-    }
+  if (!replay_iterations(p, n_iter, [&](hipStream_t) {
+        primal(a.xbuf);
+        hipLaunchKernelGGL((k_dual_x<T>), g, b, 0, s, a);
+      })) {
+    p->err = "graph capture or launch of the dual iteration failed";
+    return BQ_EDEVICE;
   }
   if (hipMemcpyAsync(a.R, a.P, 3 * V * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
     p->err = "copy failed";
@@ -582,7 +570,7 @@ static bq_status run_rank_once(bq_prox* p, const void* v, double tau, const void
 template <typename T, int R>
 static bq_status run_rank(bq_prox* p, const void* v, double tau, const void* U, double lam, int tv, int cset,
                           int n_iter, void* x_out, void* P_io, bq_prox_stats* stats) {
-  if (hipEventRecord(p->ev, p->stream) != hipSuccess || hipStreamWaitEvent(p->own, p->ev, 0) != hipSuccess) {
+  if (!order_after_caller(p)) {
     p->err = "stream synchronisation failed";
     return BQ_EDEVICE;
   }
