@@ -60,6 +60,7 @@ ITER_VEC_UNITS = 13.0
 # 2.4 GHz.  The code is built with packed FP32 disabled, so the 157.3
 # TFLOP/s packed figure is not reachable by it.
 FP32_VALU_PEAK_TFLOPS = 78.6
+FP64_VALU_PEAK_TFLOPS = 78.6
 
 
 def yc_flops_per_line(N):
@@ -137,18 +138,163 @@ def measured_traffic(kernel):
             "dispatches": int(kv.get("dispatches", 0))}
 
 
+def kernel_name(pas, N, prec):
+    """The kernel that runs pass `pas` of G at grid N in precision prec
+    (register kernels of padded lines up to 128 and for the complex64 y pass
+    at 256, parity-split lines for the other 256 passes, LDS Stockham
+    kernels for the other grids)."""
+    T = "float" if prec == "f32" else "double"
+    if pas in ("xf", "xi", "xy"):
+        return f"k_{pas}<{T},{N}>"
+    if N in (16, 32, 64, 128):
+        suf = "_p"
+    elif N == 256:
+        suf = "_p" if (pas == "yc" and prec == "f32") else "_r"
+    else:
+        suf = ""
+    return f"k_{pas}{suf}<{T},{N}>"
+
+
+def measure_gradient(w, dev, steps, warmup, autotune=True, prec=None, ctx_kw=None, label=None):
+    """Time `steps` calls of the batched mini-batch gradient of workload w
+    (after `warmup` untimed calls that also time every pass of G), inputs
+    resident on the device.  Measurements from the library's own forward
+    model (FP32, tol 1e-6; the Born model for a Born workload) plus noise.
+    Returns the figures of the timed steps and the context's last gradient
+    (for cross-precision checks)."""
+    import torch
+
+    import synthetic as syn
+    from paper_2307_02043_amd import LSContext
+    from paper_2307_02043_amd import _lib as L
+
+    prec = prec or w.precision
+    N, B = w.N, w.B
+    V = N ** 3
+    xt = syn.scattering_potential(syn.make_phantom(w))
+    dirs = syn.workload_directions(w)
+    idx = syn.batch_indices(w)
+    scale = 1.0 / B
+    t = time.perf_counter()
+    fwd = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", w.model, tol=1e-6, max_iter=w.max_iter)
+    yc, _ = fwd.forward(torch.from_numpy(xt).to(dev, torch.float32), idx)
+    fwd.close()
+    y = syn.add_noise(yc.cpu().numpy(), w.snr_db, np.random.default_rng(w.seed("noise")))
+    rd, cd = (torch.float32, torch.complex64) if prec == "f32" else (torch.float64, torch.complex128)
+    t = time.perf_counter()
+    ctx = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, prec, w.model, tol=w.tol, max_iter=w.max_iter,
+                    **(ctx_kw or {}))
+    setup_s = time.perf_counter() - t
+    tune = None
+    if autotune and w.model == "ls":
+        t = time.perf_counter()
+        tune = ctx.autotune(B)
+        tune["s"] = round(time.perf_counter() - t, 2)
+    lib = L.load()
+    xe = torch.from_numpy(w.x_eval_scale * xt).to(dev, rd)
+    yt = torch.from_numpy(y).to(dev, cd)
+
+    def read_timers():
+        ms_, n_ = {}, {}
+        for pid, name in enumerate(L.PASS_NAMES):
+            ms = L.ct.c_double()
+            n = L.ct.c_longlong()
+            lib.bq_timing_get(ctx._h, pid, L.ct.byref(ms), L.ct.byref(n))
+            if n.value:
+                ms_[name], n_[name] = ms.value, n.value
+        return ms_, n_
+
+    # Warmup steps time every pass (two HIP events per launch): per-pass
+    # breakdown and the choice of the dominant pass.  The timed steps then
+    # record events around the dominant pass only, which keeps the event
+    # overhead out of the step time (all passes if there is no warmup).
+    lib.bq_timing(ctx._h, L.BQ_TIMING_ALL)
+    for i in range(warmup):
+        _, loss, info = ctx.grad(xe, yt, idx, scale)
+        log(f"{label or w.name} warmup {i}: loss {loss:.6e} iters fwd {info.iters_fwd} adj {info.iters_adj}")
+    torch.cuda.synchronize()
+    lib.bq_timing(ctx._h, 0)
+    warm_ms, warm_n = read_timers()
+    if warm_ms:
+        dom = max((k for k in warm_ms if k in PASS_UNITS), key=lambda k: warm_ms[k])
+        mask = 1 << L.PASS_NAMES.index(dom)
+    else:
+        dom, mask = None, L.BQ_TIMING_ALL
+    lib.bq_timing(ctx._h, mask)
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        g, loss, info = ctx.grad(xe, yt, idx, scale)
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lib.bq_timing(ctx._h, 0)
+    log(f"{label or w.name} {prec}: {steps} steps in {elapsed:.3f} s")
+    pass_ms, pass_n = read_timers()
+    if dom is None:
+        dom = max((k for k in pass_ms if k in PASS_UNITS), key=lambda k: pass_ms[k])
+        warm_ms, breakdown_steps = pass_ms, steps
+    else:
+        breakdown_steps = warmup
+    apps = sum(sum(inf.green_apps) for inf in infos)
+    iters = sum(sum(inf.iters_fwd) + sum(inf.iters_adj) for inf in infos)
+    csz = 8 if prec == "f32" else 16
+    alg_bytes = apps * PASS_UNITS[dom] * V * csz
+    achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
+    kname = kernel_name(dom, N, prec)
+    avg_ms = pass_ms[dom] / pass_n[dom]
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "bytes_per_system_application": PASS_UNITS[dom] * V * csz,
+                "system_applications": apps, "launches": pass_n[dom],
+                "avg_launch_ms": round(avg_ms, 4)}
+    if dom == "yc":
+        # the same launches against the vector-ALU roof (4 classes x N^2 lines per system)
+        flops = apps * 4 * N * N * yc_flops_per_line(N)
+        tf = flops / (pass_ms[dom] * 1e-3) / 1e12
+        peak = FP32_VALU_PEAK_TFLOPS if prec == "f32" else FP64_VALU_PEAK_TFLOPS
+        roofline["alu_view"] = {"achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                                "frac": round(tf / peak, 4), "flops_per_line": yc_flops_per_line(N)}
+    whole_bytes = (apps * G_UNITS + iters * ITER_VEC_UNITS) * V * csz
+    whole = whole_bytes / elapsed / 1e9
+    last = infos[-1]
+    res = {
+        "value": round(B * steps / elapsed, 4), "unit": "illum-solves/s",
+        "ms_per_step": round(elapsed / steps * 1e3, 3), "steps": steps, "warmup": warmup,
+        "roofline": roofline,
+        "whole_call": {"scope": "whole gradient call, model bytes", "achieved": round(whole, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(whole / HBM_PEAK_GBS, 4),
+                       "bytes_per_step": whole_bytes / steps},
+        "solver": {"status": max(inf.status for inf in infos), "bicgstab_iters_per_step": iters / steps,
+                   "green_apps_per_step": apps / steps, "bicgstab_iters_per_s": round(iters / elapsed, 1),
+                   "iters_fwd": list(last.iters_fwd), "iters_adj": list(last.iters_adj),
+                   "setup_s": round(setup_s, 2)},
+        "passes_ms_per_step": {k: round(v / breakdown_steps, 3) for k, v in warm_ms.items()},
+        "autotune": tune,
+    }
+    ctx.close()
+    return res, g, (xt, y, dirs, idx)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4_ls128_f32")
-    ap.add_argument("--plain-steps", type=int, default=1,
-                    help="timed steps of the plain FP64 path (0: skip)")
+    ap.add_argument("--plain-steps", type=int, default=5,
+                    help="timed steps of the plain FP64 path, after one warmup step (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=10,
-                    help="BiCGSTAB iterations of the oracle sample (0: skip)")
+                    help="BiCGSTAB iterations of the oracle sample with all cores (0: skip)")
+    ap.add_argument("--cpu-iters-1t", type=int, default=2,
+                    help="BiCGSTAB iterations of the single-thread oracle sample (0: skip)")
+    ap.add_argument("--configs", default="c1_ls32_f64,c2_born64_f32,c3_ls96_f32,c5_ls256_f32,c6_ls128_strong",
+                    help="other workloads whose gradient is timed alongside ('' to skip)")
     ap.add_argument("--prox-workload", default="c5_ls256_f32",
                     help="workload whose weighted prox is timed alongside ('' to skip)")
+    ap.add_argument("--prox-small", default="c1_ls32_f64,c2_born64_f32",
+                    help="small workloads whose prox latency is timed ('' to skip)")
     ap.add_argument("--qn-iters", type=int, default=9,
                     help="outer iterations of the quasi-Newton method timed alongside (0: skip)")
     ap.add_argument("--autotune", type=int, default=1,
@@ -168,7 +314,6 @@ def main():
 
     import synthetic as syn
     from paper_2307_02043_amd import LSContext
-    from paper_2307_02043_amd import _lib as L
 
     w = syn.WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
@@ -178,132 +323,34 @@ def main():
     N, B = w.N, w.B
     V = N ** 3
     log(f"workload {w.name}: N={N} B={B} of L={w.L}")
-    xt = syn.scattering_potential(syn.make_phantom(w))
-    dirs = syn.workload_directions(w)
-    idx = syn.batch_indices(w)
+
+    # ---- batched FP32 path (the headline) -----------------------------------
+    head, g, (xt, y, dirs, idx) = measure_gradient(w, dev, args.steps, args.warmup, bool(args.autotune))
     scale = 1.0 / B
-
-    # measurements from the library's own forward model + noise
-    t = time.perf_counter()
-    fwd = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=1e-6,
-                    max_iter=w.max_iter)
-    yc, _ = fwd.forward(torch.from_numpy(xt).to(dev, torch.float32), idx)
-    fwd.close()
-    y = syn.add_noise(yc.cpu().numpy(), w.snr_db, np.random.default_rng(w.seed("noise")))
-    log(f"measurements ready ({time.perf_counter() - t:.1f} s)")
-
-    # ---- batched FP32 path ------------------------------------------------
-    t = time.perf_counter()
-    ctx = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol,
-                    max_iter=w.max_iter)
-    setup_s = time.perf_counter() - t
-    tune = None
-    if args.autotune:
-        t = time.perf_counter()
-        tune = ctx.autotune(B)
-        tune["s"] = round(time.perf_counter() - t, 2)
-        log(f"autotune: x tile rows {tune['x_tile_rows'] or 'default'}, z-forward threads "
-            f"{tune['zf_threads'] or 'default'} ({tune['ms_default']:.2f} -> {tune['ms_tuned']:.2f} ms "
-            f"per timed solve)")
-    lib = L.load()
-    xe = torch.from_numpy(0.5 * xt).to(dev, torch.float32)
-    yt = torch.from_numpy(y).to(dev, torch.complex64)
-    def read_timers():
-        ms_, n_ = {}, {}
-        for pid, name in enumerate(L.PASS_NAMES):
-            ms = L.ct.c_double()
-            n = L.ct.c_longlong()
-            lib.bq_timing_get(ctx._h, pid, L.ct.byref(ms), L.ct.byref(n))
-            if n.value:
-                ms_[name], n_[name] = ms.value, n.value
-        return ms_, n_
-
-    # Warmup steps time every pass (two HIP events per launch): per-pass
-    # breakdown and the choice of the dominant pass.  The timed steps then
-    # record events around the dominant pass only, which keeps the event
-    # overhead out of the step time (all passes if there is no warmup).
-    lib.bq_timing(ctx._h, L.BQ_TIMING_ALL)
-    for i in range(args.warmup):
-        _, loss, info = ctx.grad(xe, yt, idx, scale)
-        log(f"warmup {i}: loss {loss:.6e} iters fwd {info.iters_fwd} adj {info.iters_adj}")
-    torch.cuda.synchronize()
-    lib.bq_timing(ctx._h, 0)
-    warm_ms, warm_n = read_timers()
-    if warm_ms:
-        dom = max((k for k in warm_ms if k in PASS_UNITS), key=lambda k: warm_ms[k])
-        mask = 1 << L.PASS_NAMES.index(dom)
-    else:
-        dom, mask = None, L.BQ_TIMING_ALL
-    lib.bq_timing(ctx._h, mask)
-    infos = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        g, loss, info = ctx.grad(xe, yt, idx, scale)
-        infos.append(info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lib.bq_timing(ctx._h, 0)
-    elapsed = t1 - t0
-    log(f"batched f32: {args.steps} steps in {elapsed:.3f} s")
-    pass_ms, pass_n = read_timers()
-    if dom is None:
-        dom = max((k for k in pass_ms if k in PASS_UNITS), key=lambda k: pass_ms[k])
-        warm_ms, breakdown_steps = pass_ms, args.steps
-    else:
-        breakdown_steps = args.warmup
-    apps = sum(sum(inf.green_apps) for inf in infos)
-    iters = sum(sum(inf.iters_fwd) + sum(inf.iters_adj) for inf in infos)
-    value = B * args.steps / elapsed
-    status = max(inf.status for inf in infos)
-
-    # roofline of the dominant pass (its launches in the timed steps)
-    csz = 8  # complex64
-    alg_bytes = apps * PASS_UNITS[dom] * V * csz
-    achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
-    # register kernels: padded lines (_p) up to 128 and for the 256 y pass,
-    # parity-split lines (_r) for the 256 z passes
-    sz = "_p" if N <= 128 else "_r" if N == 256 else ""
-    sy = "_p" if N <= 256 else ""
-    kname = {"yc": "k_yc" + sy, "zf": "k_zf" + sz, "zi": "k_zi" + sz,
-             "xf": "k_xf", "xi": "k_xi", "xy": "k_xy"}[dom]
-    avg_ms = pass_ms[dom] / pass_n[dom]
-    roofline = {"bound": "hbm", "kernel": f"{kname}<float,{N}>", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
-                "bytes_per_system_application": PASS_UNITS[dom] * V * csz,
-                "system_applications": apps, "launches": pass_n[dom],
-                "avg_launch_ms": round(avg_ms, 4)}
-    tr = measured_traffic(f"{kname}<float,{N}>") if B == 16 else None
+    roofline = head["roofline"]
+    dom_kernel = roofline["kernel"]
+    tr = measured_traffic(dom_kernel) if B == 16 else None
     if tr is not None:
         # counters were taken on launches with every system active; scaled to
         # the timed launches like `achieved` (system applications per launch)
+        apps, launches = roofline["system_applications"], roofline["launches"]
         per_app = tr["full_dispatch_bytes"] / tr["systems_per_dispatch"]
-        per_launch = per_app * apps / pass_n[dom]
+        per_launch = per_app * apps / launches
         roofline["traffic"] = round(per_launch)
-        tr["measured_gbs"] = round(per_launch / (avg_ms * 1e-3) / 1e9, 1)
-        tr["vs_algorithmic"] = round(per_app / (PASS_UNITS[dom] * V * csz), 4)
+        tr["measured_gbs"] = round(per_launch / (roofline["avg_launch_ms"] * 1e-3) / 1e9, 1)
+        tr["vs_algorithmic"] = round(per_app / roofline["bytes_per_system_application"], 4)
         roofline["traffic_detail"] = tr
-    if dom == "yc":
-        # the same launches against the vector-ALU roof (4 classes x N^2 lines per system)
-        flops = apps * 4 * N * N * yc_flops_per_line(N)
-        tf = flops / (pass_ms[dom] * 1e-3) / 1e12
-        roofline["alu_view"] = {"achieved": round(tf, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4),
-                                "flops_per_line": yc_flops_per_line(N)}
-    whole_bytes = (apps * G_UNITS + iters * ITER_VEC_UNITS) * V * csz
-    whole = whole_bytes / elapsed / 1e9
-    whole_call = {"scope": "whole gradient call, model bytes", "achieved": round(whole, 1),
-                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(whole / HBM_PEAK_GBS, 4),
-                  "bytes_per_step": whole_bytes / args.steps}
-    ctx.close()
+    value = head["value"]
+    iters = head["solver"]["bicgstab_iters_per_step"] * args.steps
 
     # ---- plain FP64 path ----------------------------------------------------
     plain = None
     if args.plain_steps > 0:
         ctx64 = LSContext(N, w.h_um, w.lambda0_um, w.n_b, dirs, "f64", "ls", tol=w.tol,
                           max_iter=w.max_iter, plain=True)
-        x64 = torch.from_numpy(0.5 * xt).to(dev)
+        x64 = torch.from_numpy(w.x_eval_scale * xt).to(dev)
         y64 = torch.from_numpy(y).to(dev)
+        ctx64.grad(x64, y64, idx, scale)  # warmup
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         pinfos = []
@@ -316,51 +363,45 @@ def main():
         gerr = float(torch.linalg.norm(g.double() - g64) / torch.linalg.norm(g64))
         plain = {"value": round(B * args.plain_steps / pel, 3), "unit": "illum-solves/s",
                  "ms_per_step": round(pel / args.plain_steps * 1e3, 2), "steps": args.plain_steps,
-                 "bicgstab_iters_per_s": round(piters / pel, 1),
+                 "warmup": 1, "bicgstab_iters_per_s": round(piters / pel, 1),
                  "iters_per_step": piters / args.plain_steps,
-                 "f32_vs_f64_grad_rel_err": gerr}
-        log(f"plain f64: {pel:.2f} s, grad rel diff f32 vs f64 {gerr:.2e}")
+                 "f32_vs_f64_grad_rel_diff": gerr}
+        log(f"plain f64: {pel / args.plain_steps * 1e3:.2f} ms per step, grad rel diff f32 vs f64 {gerr:.2e}")
         ctx64.close()
 
     # ---- CPU oracle baseline --------------------------------------------------
     cpu = None
     if args.cpu_iters > 0:
-        from oracle import lsmodel
-        cores = min(os.cpu_count() or 1, 16)
-        geom = lsmodel.Geometry(N=N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
-        t = time.perf_counter()
-        model = lsmodel.LSModel(geom, workers=cores)
-        log(f"oracle transfer function ({time.perf_counter() - t:.1f} s)")
-        xe64 = 0.5 * xt
-        uin = lsmodel.incident_field(geom, dirs[idx[0]])
-        t = time.perf_counter()
-        model.solve_forward(xe64, uin, 0.0, args.cpu_iters)  # tol 0: runs the cap
-        t_iter = (time.perf_counter() - t) / args.cpu_iters
-        mean_iters = iters / (args.steps * B)
-        extra = 3  # initial residuals of both solves + adjoint right-hand side
-        t_ill = t_iter * mean_iters + extra * t_iter / 2
-        cpu = {"value": round(1.0 / t_ill, 5), "unit": "illum-solves/s", "cores": cores,
-               "kind": "oracle",
-               "sample": (f"one illumination of this workload: the oracle's FP64 BiCGSTAB run for "
-                          f"{args.cpu_iters} iterations ({t_iter:.2f} s each, scipy.fft with "
-                          f"{cores} workers), extrapolated to the GPU-observed "
-                          f"{mean_iters:.1f} iterations per illumination (forward + adjoint) plus "
-                          f"3 extra applications of G")}
-        log(f"oracle: {t_iter:.2f} s per BiCGSTAB iteration")
+        cpu = cpu_baseline(w, xt, dirs, idx, iters / (args.steps * B), args.cpu_iters, args.cpu_iters_1t)
+
+    # ---- the other workloads ------------------------------------------------
+    configs = {}
+    for name in [c for c in args.configs.split(",") if c]:
+        cw = syn.WORKLOADS[name]
+        steps = 3 if cw.N >= 256 else 5 if cw.N >= 128 else 20
+        r, _, _ = measure_gradient(cw, dev, steps, 1, bool(args.autotune))
+        r["workload"] = (f"{cw.name}: {'first-Born' if cw.model == 'born' else 'Lippmann-Schwinger'} "
+                         f"mini-batch gradient, {cw.N}^3, batch {cw.B} of {cw.L}, "
+                         f"{'complex64' if cw.precision == 'f32' else 'complex128'}, tol {cw.tol:g}, "
+                         f"x = {cw.x_eval_scale:g} x_true")
+        configs[name] = r
 
     # ---- propagated detector plane (angular spectrum), same workload ---------
-    det = bench_detprop(w, dev, xt, dirs, idx, scale, args.steps, 1e3 * elapsed / args.steps) \
+    det = bench_detprop(w, dev, xt, dirs, idx, scale, args.steps, head["ms_per_step"]) \
         if args.steps > 0 else None
 
     # ---- outer iteration of the method on the same workload -----------------
     qn = None
     if args.qn_iters > 0:
-        qn = bench_qn(w, dev, xt, dirs, args.qn_iters, 1e3 * elapsed / args.steps, plan=tune)
+        qn = bench_qn(w, dev, xt, dirs, args.qn_iters, head["ms_per_step"], plan=head["autotune"])
 
     # ---- weighted TV prox (second kernel of the method) ---------------------
     prox = None
     if args.prox_workload:
         prox = bench_prox(syn.WORKLOADS[args.prox_workload], dev)
+    prox_small = {}
+    for name in [c for c in args.prox_small.split(",") if c]:
+        prox_small[name] = bench_prox_latency(syn.WORKLOADS[name], dev)
 
     out = {
         "metric": METRIC,
@@ -369,7 +410,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -380,20 +421,59 @@ def main():
                                 f"fields, FP64 reductions, BiCGSTAB tol {w.tol:g}"),
                    "grid": N, "batch": B, "illuminations": w.L, "tol": w.tol},
         "roofline": roofline,
-        "whole_call": whole_call,
+        "whole_call": head["whole_call"],
         "cpu_baseline": cpu,
         "plain_f64": plain,
         "speedup_vs_plain_f64": (round(value / plain["value"], 2) if plain else None),
-        "solver": {"status": status, "bicgstab_iters_per_step": iters / args.steps,
-                   "green_apps_per_step": apps / args.steps,
-                   "bicgstab_iters_per_s": round(iters / elapsed, 1), "setup_s": round(setup_s, 2)},
-        "passes_ms_per_step": {k: round(v / breakdown_steps, 3) for k, v in warm_ms.items()},
-        "autotune": tune,
+        "solver": head["solver"],
+        "passes_ms_per_step": head["passes_ms_per_step"],
+        "autotune": head["autotune"],
+        "configs": configs,
         "prox": prox,
+        "prox_latency": prox_small,
         "qn": qn,
         "detector_propagation": det,
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, xt, dirs, idx, mean_iters, iters_all, iters_1t):
+    """The oracle (never tuned) on the host cores: FP64 BiCGSTAB iterations
+    of one illumination of the workload, with scipy.fft on all cores (at
+    most 16) and, sharing its transfer function, on one thread; each
+    extrapolated to an illumination's forward and adjoint solves at the
+    GPU-observed iteration count plus the 3 extra applications of G."""
+    from oracle import lsmodel
+    cores = min(os.cpu_count() or 1, 16)
+    geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+    t = time.perf_counter()
+    model = lsmodel.LSModel(geom, workers=cores)
+    log(f"oracle transfer function ({time.perf_counter() - t:.1f} s)")
+    xe64 = w.x_eval_scale * xt
+    uin = lsmodel.incident_field(geom, dirs[idx[0]])
+    extra = 3  # initial residuals of both solves + adjoint right-hand side
+
+    def timed(m, n):
+        t0 = time.perf_counter()
+        m.solve_forward(xe64, uin, 0.0, n)  # tol 0: runs the cap
+        t_iter = (time.perf_counter() - t0) / n
+        return t_iter, 1.0 / (t_iter * mean_iters + extra * t_iter / 2)
+
+    t_iter, val = timed(model, iters_all)
+    out = {"value": round(val, 5), "unit": "illum-solves/s", "cores": cores, "kind": "oracle",
+           "sample": (f"one illumination of this workload: the oracle's FP64 BiCGSTAB run for "
+                      f"{iters_all} iterations ({t_iter:.2f} s each, scipy.fft with {cores} workers), "
+                      f"extrapolated to the GPU-observed {mean_iters:.1f} iterations per illumination "
+                      f"(forward + adjoint) plus 3 extra applications of G")}
+    log(f"oracle: {t_iter:.2f} s per BiCGSTAB iteration on {cores} cores")
+    if iters_1t > 0:
+        one = lsmodel.LSModel(geom, ghat_P=model.ghat, workers=1)
+        t1, val1 = timed(one, iters_1t)
+        out["single_thread"] = {"value": round(val1, 5), "unit": "illum-solves/s", "cores": 1,
+                                "s_per_bicgstab_iter": round(t1, 3),
+                                "sample": f"{iters_1t} iterations of the same solve, scipy.fft on one thread"}
+        log(f"oracle: {t1:.2f} s per BiCGSTAB iteration on one thread")
+    return out
 
 
 def bench_detprop(w, dev, xt, dirs, idx, scale, steps, base_ms, d_um=1.0):
@@ -550,6 +630,37 @@ def bench_prox(w, dev, reps=2):
                            "roofline": {"bound": "hbm", "scope": "whole call", "achieved": round(achieved0, 1),
                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                         "frac": round(achieved0 / HBM_PEAK_GBS, 4), "bytes": units0 * V * 4}}}
+
+
+def bench_prox_latency(w, dev, reps=5):
+    """Latency of one weighted prox of a small workload (its TV kind,
+    precision, metric tau I + u u^T, lambda, iteration count): images that
+    stay in the last-level cache, where the launch sequence, not HBM,
+    sets the time."""
+    import torch
+
+    import synthetic as syn
+    from paper_2307_02043_amd import WProx
+
+    v, tau, u = syn.prox_inputs(w)
+    dt = torch.float32 if w.precision == "f32" else torch.float64
+    vt = torch.from_numpy(v).to(dev, dt)
+    ut = torch.from_numpy(u).to(dev, dt)
+    px = WProx(v.shape, w.precision)
+    x, info = px(vt, tau, ut, w.prox_lambda, w.prox_tv, "nonneg", w.prox_iters)  # warmup
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        x, info = px(vt, tau, ut, w.prox_lambda, w.prox_tv, "nonneg", w.prox_iters)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / reps
+    px.close()
+    log(f"prox latency {w.name}: {el * 1e3:.2f} ms per call of {w.prox_iters} dual iterations")
+    return {"workload": (f"{w.name} prox: {w.N}^3 {w.prox_tv}-TV, nonnegativity, metric tau I + u u^T, "
+                         f"lambda {w.prox_lambda:g}, {w.prox_iters} dual iterations, "
+                         f"{'FP32' if w.precision == 'f32' else 'FP64'}"),
+            "ms_per_call": round(el * 1e3, 3), "us_per_dual_iter": round(el / w.prox_iters * 1e6, 2),
+            "root_evaluations": info.newton_total}
 
 
 if __name__ == "__main__":

@@ -47,6 +47,7 @@ class Workload:
     prox_lambda: float = 1e-3
     prox_iters: int = 0
     prox_tau: float = 1.0
+    x_eval_scale: float = 0.5      # gradients are evaluated at this multiple of x_true
     extra: dict = field(default_factory=dict)
 
     @property
@@ -79,6 +80,15 @@ WORKLOADS = {
                              model="ls", precision="f32", tol=1e-5,
                              max_iter=300, phantom="cell", contrast_scale=1.5,
                              prox_tv="iso", prox_lambda=1e-3, prox_iters=200),
+    # stand-in for the strongly scattering simulated sample of Section 6.1
+    # (maximal index 1.43 in a 1.333 medium, 60 illuminations in a 42 degree
+    # cone, mini-batches of 15 = 60 / 4 subsets), on the 128^3 grid of
+    # quarter-wavelength voxels: a solid cell body of delta n 0.06 with 20
+    # nucleoli of 0.097, gradient evaluated at the phantom itself
+    "c6_ls128_strong": Workload("c6_ls128_strong", 6, N=128, L=60, B=15,
+                                model="ls", precision="f32", tol=1e-5,
+                                max_iter=300, phantom="cell_solid",
+                                max_polar_deg=42.0, x_eval_scale=1.0),
 }
 
 
@@ -152,6 +162,22 @@ def phantom_cell(N: int, h: float, rng: np.random.Generator,
     return dn * scale
 
 
+def phantom_cell_solid(N: int, h: float, rng: np.random.Generator,
+                       body_dn: float = 0.06, nucleolus_dn: float = 0.097) -> np.ndarray:
+    """Solid ellipsoidal cell body (semi-axes 0.40, 0.35, 0.30 of the
+    domain edge) holding 20 nucleoli of a higher index."""
+    Z, Y, X = _coords(N, h)
+    a = np.array([0.40, 0.35, 0.30]) * N * h
+    q = (X / a[0]) ** 2 + (Y / a[1]) ** 2 + (Z / a[2]) ** 2
+    dn = np.where(q <= 1.0, body_dn, 0.0)
+    for _ in range(20):
+        r = rng.uniform(1.5, 4.0) * (N / 96.0) * h
+        c = rng.uniform(-1.0, 1.0, size=3) * (a - r) * 0.6
+        inside = ((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) <= r * r
+        dn = np.where(inside, nucleolus_dn, dn)
+    return dn
+
+
 def make_phantom(w: Workload) -> np.ndarray:
     rng = np.random.default_rng(w.seed("phantom"))
     if w.phantom == "ellipsoids":
@@ -160,6 +186,8 @@ def make_phantom(w: Workload) -> np.ndarray:
         return phantom_beads(w.N, w.h_um, rng) * w.contrast_scale
     if w.phantom == "cell":
         return phantom_cell(w.N, w.h_um, rng, scale=w.contrast_scale)
+    if w.phantom == "cell_solid":
+        return phantom_cell_solid(w.N, w.h_um, rng) * w.contrast_scale
     raise ValueError(w.phantom)
 
 

@@ -2,7 +2,7 @@
 tests that the oracle cannot finish inside a test (hours of FP64 CPU work
 otherwise repeated on every run).  Calls only oracle/ and synthetic/.
 
-    python tests/golden/make_fullsize_refs.py [grad|prox|all] [workers]
+    python tests/golden/make_fullsize_refs.py [grad|strong|prox|all] [workers]
 
 grad: the 256^3 workload with contrast x1.5 (c5_ls256_f32), the first two
       illuminations of its mini-batch.  Measurements y = H(x_true) (oracle
@@ -11,6 +11,11 @@ grad: the 256^3 workload with contrast x1.5 (c5_ls256_f32), the first two
       widened to complex128).  The gradient and loss at x = 0.5 x_true with
       scale 1/2 (oracle solves at tol 1e-11), kept at 8192 seeded voxels
       together with whole-array sums.
+strong: the strongly scattering 128^3 workload (c6_ls128_strong), its first
+      two mini-batch illuminations: measurements H(x_true) (tol 1e-13) plus
+      30 dB noise, stored as complex128, and the FP64 gradient and loss at
+      x_true with scale 1/2 (tol 1e-13 on both sides of the comparison),
+      kept at 8192 seeded voxels, with the iteration counts.
 prox: the weighted TV prox of the same workload: iso TV, nonnegativity,
       metric tau I + u u^T (rank one), lambda 1e-3, 200 dual iterations
       (Section 4.1 iteration, Theorem 3.1 projection), kept at 8192 seeded
@@ -84,6 +89,26 @@ def make_grad(workers: int) -> None:
              inputs=array_digest(x, dirs))
 
 
+def make_strong(workers: int) -> None:
+    w = syn.WORKLOADS["c6_ls128_strong"]
+    geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+    t0 = time.time()
+    m = lsmodel.LSModel(geom, workers=workers)
+    xt = syn.scattering_potential(syn.make_phantom(w))
+    dirs = syn.workload_directions(w)
+    idx = [int(i) for i in syn.batch_indices(w)[:2]]
+    yc, st = m.forward(xt, dirs, idx, 1e-13, 1000)
+    print(f"forward {time.time() - t0:.0f} s, iterations {[s[0] for s in st]}", flush=True)
+    y = syn.add_noise(yc, w.snr_db, np.random.default_rng(w.seed("noise")))
+    x = w.x_eval_scale * xt
+    g, f, st = m.grad(x, y, dirs, idx, 0.5, 1e-13, 1000)
+    print(f"gradient {time.time() - t0:.0f} s, iterations {st}", flush=True)
+    sel = sample_index(g.size, 7128)
+    np.savez(os.path.join(HERE, "c6_grad128_strong_b2.npz"), idx=np.array(idx, np.int32), y=y, loss=f,
+             sel=sel, g_sel=g.ravel()[sel], g_norm=np.linalg.norm(g), iters=np.array(st, np.int32),
+             digest=source_digest(GRAD_SOURCES), inputs=array_digest(x, dirs))
+
+
 def make_prox() -> None:
     w = syn.WORKLOADS["c5_ls256_f32"]
     v, tau, u = syn.prox_inputs(w)
@@ -102,5 +127,7 @@ if __name__ == "__main__":
     workers = int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1)
     if what in ("grad", "all"):
         make_grad(workers)
+    if what in ("strong", "all"):
+        make_strong(workers)
     if what in ("prox", "all"):
         make_prox()
