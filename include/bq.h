@@ -266,6 +266,19 @@ typedef struct {
 } bq_ctx_info;
 bq_status bq_get_info(const bq_ctx* ctx, bq_ctx_info* out);
 
+/* Self-check of the library's own addressing (no operation of the paper;
+ * host code only, no GPU needed).  The padded-line passes of G read and
+ * write through raw buffer resources, where an access past the resource's
+ * size reads zero or is dropped instead of faulting.  For every grid and
+ * precision those passes are built for, this enumerates every offset their
+ * launch grids can form (and the y pass's workgroup-to-slice mapping for
+ * batches of 1..40) and checks that each resource is under 2^31 bytes, lies
+ * inside its allocation, and contains every access without 32-bit wrap.
+ *   report    host, receives a message (may be NULL); report_len its size
+ *   accesses  host, receives the number of accesses checked (may be NULL)
+ * Returns the number of violations (0: all in range). */
+int bq_audit_raw_ranges(char* report, int report_len, long long* accesses);
+
 /* ---------------------------------------------------------------------
  * Weighted proximal mapping of constrained TV
  * --------------------------------------------------------------------- */

@@ -27,7 +27,7 @@ BQ_WPROX_NOALLOC_SCRATCH = 96 << 20
 
 EXPORTED = ("bq_create", "bq_destroy", "bq_last_error", "bq_forward", "bq_fields",
             "bq_grad", "bq_grad_ws", "bq_loss", "bq_green_apply", "bq_timing", "bq_timing_get", "bq_autotune", "bq_set_plan", "bq_set_batch_limit",
-            "bq_set_breakdown_floor", "bq_get_info", "bq_prox_create", "bq_prox_destroy",
+            "bq_set_breakdown_floor", "bq_get_info", "bq_audit_raw_ranges", "bq_prox_create", "bq_prox_destroy",
             "bq_prox_last_error", "bq_wprox", "bq_wprox_noalloc", "bq_qn_create", "bq_qn_destroy", "bq_qn_last_error",
             "bq_qn_step")
 
@@ -111,6 +111,7 @@ def load() -> ct.CDLL:
         "bq_set_batch_limit": ([P, I], I),
         "bq_set_breakdown_floor": ([P, D], I),
         "bq_get_info": ([P, ct.POINTER(CtxInfo)], I),
+        "bq_audit_raw_ranges": ([ct.c_char_p, I, ct.POINTER(ct.c_longlong)], I),
         "bq_prox_create": ([I, I, I, I, P, ct.POINTER(P)], I),
         "bq_prox_destroy": ([P], I),
         "bq_prox_last_error": ([P], ct.c_char_p),

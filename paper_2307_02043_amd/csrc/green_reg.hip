@@ -14,7 +14,12 @@
 // pass and of the transform sides of the z passes are raw buffer accesses
 // with the stride in the scalar offset, which keeps address arithmetic off
 // the vector ALU -- the y pass is bound by vector-ALU issue.
+#include <cstdio>
+#include <string>
+#include <vector>
+
 #include "bq_kernels.h"
+#include "raw_offsets.h"
 
 namespace bq {
 
@@ -405,13 +410,14 @@ __global__ void __launch_bounds__(NTH) k_zf_p(PassArgs<T> a) {
   line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
   // padded frequency kp = k1 + R1 k2 (k1 = j + R2 i): class kp & 1 = j & 1,
   // plane kp >> 1; the two classes of system b are consecutive volumes
-  const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * V, 2 * V * SZ);
-  const uint32_t vo = (uint32_t)((j & 1) * N * N * N + (j >> 1) * N * N + L) * SZ;
+  using O = PadRaw<N, R1, R2, SZ>;
+  const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * V, O::z_bytes);
+  const uint32_t vo = O::z_v(j, L);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
-      bstore<T, true>(d[i * R2 + k2], rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
+      bstore<T, true>(d[i * R2 + k2], rz, vo, O::z_s(i, k2));
 }
 
 // y columns of class (pz, px), line L = kz N + kx
@@ -426,10 +432,8 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   // (class, line block) take consecutive slots of the same XCD, so the
   // transfer-function slab they share is fetched into that XCD's L2 once.
   constexpr int NLB = N * N / LPW;
-  const int h = blockIdx.x, sl = h >> 3;
-  const int b = sl % a.B;
-  const int q = (sl / a.B) * 8 + (h & 7);
-  const int cls = q / NLB, lb = q - cls * NLB, pz = cls >> 1, px = cls & 1;
+  const YcSlot slot = yc_slot(blockIdx.x, a.B, NLB);
+  const int b = slot.b, cls = slot.cls, lb = slot.lb, pz = cls >> 1, px = cls & 1;
   const int tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
   load_twtab_pad<T, N, R1, R2>(twt, a.twH, tid);
@@ -437,25 +441,26 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   const int L = lb * LPW + line;
   const int kz = L / N, kx = L - kz * N;
   // column: one resource per (system, class) slice, element y at (kz N + y) N + kx
-  const brsrc rc = make_rsrc(a.xh + ((size_t)b * 4 + cls) * V, V * SZ);
-  const uint32_t vo = (uint32_t)(kz * N * N + kx + j * N) * SZ;
+  using O = PadRaw<N, R1, R2, SZ>;
+  const brsrc rc = make_rsrc(a.xh + ((size_t)b * 4 + cls) * V, O::y_bytes);
+  const uint32_t vo = O::y_v(kz, kx, j);
   C<T> d[R1];
 #pragma unroll
-  for (int m = 0; m < R1; ++m) d[m] = (m < H) ? bload<T, true>(rc, vo, (uint32_t)(m * R2 * N) * SZ) : C<T>{0, 0};
+  for (int m = 0; m < R1; ++m) d[m] = (m < H) ? bload<T, true>(rc, vo, O::y_s(m)) : C<T>{0, 0};
   // padded frequency kp = k1 + R1 k2 (k1 = j + R2 i) is py class kp & 1 = j & 1
   // at index kp >> 1; classes (pz, 0, px) and (pz, 1, px) are 2V apart
-  const brsrc rg = make_rsrc(a.ghat + (size_t)(pz * 4 + px) * V, 3 * V * SZ);
-  const uint32_t vg = (uint32_t)((j & 1) * 2 * N * N * N + kz * N * N + kx + (j >> 1) * N) * SZ;
+  const brsrc rg = make_rsrc(a.ghat + (size_t)(pz * 4 + px) * V, O::g_bytes);
+  const uint32_t vg = O::g_v(j, kz, kx);
   __syncthreads();
   line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
-      d[i * R2 + k2] = cmul(d[i * R2 + k2], bload<T>(rg, vg, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N) * SZ));
+      d[i * R2 + k2] = cmul(d[i * R2 + k2], bload<T>(rg, vg, O::g_s(i, k2)));
   line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
 #pragma unroll
-  for (int m = 0; m < H; ++m) bstore<T, true>(d[m], rc, vo, (uint32_t)(m * R2 * N) * SZ);
+  for (int m = 0; m < H; ++m) bstore<T, true>(d[m], rc, vo, O::y_s(m));
 }
 
 // z lines, inverse (first N outputs of the padded inverse), epilogue
@@ -472,14 +477,15 @@ __global__ void __launch_bounds__((rtz<T, N>())) k_zi_p(PassArgs<T> a) {
   if (sys_skip(a.state, a.mask, b)) return;
   load_twtab_pad<T, N, R1, R2, NTH>(twt, a.twH, tid);
   const int L = blockIdx.x * LPW + line;
-  const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * N * N * N, 2 * (size_t)N * N * N * SZ);
-  const uint32_t vo = (uint32_t)((j & 1) * N * N * N + (j >> 1) * N * N + L) * SZ;
+  using O = PadRaw<N, R1, R2, SZ>;
+  const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * N * N * N, O::z_bytes);
+  const uint32_t vo = O::z_v(j, L);
   C<T> d[R1];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
-      d[i * R2 + k2] = bload<T, true>(rz, vo, (uint32_t)(((R2 * i + R1 * k2) >> 1) * N * N) * SZ);
+      d[i * R2 + k2] = bload<T, true>(rz, vo, O::z_s(i, k2));
   __syncthreads();
   line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
   double red[3] = {0.0, 0.0, 0.0};
@@ -605,4 +611,125 @@ template bool zf_threads_valid<double>(int, int);
 template int reg_apply<float>(const PassArgs<float>&, hipStream_t, PassTimer*);
 template int reg_apply<double>(const PassArgs<double>&, hipStream_t, PassTimer*);
 
+// ---------------------------------------------------------------------------
+// Host-side audit of the raw buffer accesses (bq_audit_raw_ranges): every
+// offset the padded kernels can form, over their launch grids, against the
+// size of the resource it goes through.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Audit {
+  long long accesses = 0;
+  int bad = 0;
+  std::string msg;
+  void fail(const std::string& m) {
+    if (bad++ < 8) msg += m + "\n";
+  }
+  // one access: a 32-bit per-thread part and a 32-bit compile-time part
+  // (computed exactly in 64 bits), an element of esz bytes, a resource of
+  // `bytes`
+  void check(const char* what, int N, int esz, uint64_t v, uint64_t s, size_t bytes) {
+    ++accesses;
+    if (v >= (1ull << 32) || s >= (1ull << 32) || v + s >= (1ull << 32) || v + s + esz > bytes)
+      fail(std::string(what) + " N=" + std::to_string(N) + " esz=" + std::to_string(esz) + ": offset " +
+           std::to_string(v + s) + " outside " + std::to_string(bytes) + " bytes");
+  }
+  void check_resource(const char* what, int N, size_t bytes, size_t base_elems, size_t alloc_elems, int esz) {
+    if (bytes >= (1ull << 31)) fail(std::string(what) + " N=" + std::to_string(N) + ": resource over 2^31 bytes");
+    if (base_elems * esz + bytes > alloc_elems * esz)
+      fail(std::string(what) + " N=" + std::to_string(N) + ": resource passes the end of its allocation");
+  }
+};
+
+// z passes of NTH threads: lines L = block * LPW + tid % LPW, j = tid / LPW
+template <typename T, int N, int NTH>
+void audit_z(Audit& A, const char* what) {
+  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = NTH / R2, NI = R1 / R2;
+  constexpr uint32_t SZ = sizeof(C<T>);
+  using O = PadRaw<N, R1, R2, SZ>;
+  const size_t V = O::V;
+  if ((N * N) % LPW != 0) A.fail(std::string(what) + ": N^2 lines not a whole number of workgroups");
+  // system b's two classes from zh + 2 V b, inside a workspace of 2 V B (B = 1 is the tightest)
+  A.check_resource(what, N, O::z_bytes, 0, 2 * V, SZ);
+  for (int blk = 0; blk < N * N / LPW; ++blk)
+    for (int tid = 0; tid < NTH; ++tid) {
+      const int L = blk * LPW + tid % LPW, j = tid / LPW;
+      if (L < 0 || L >= N * N) A.fail(std::string(what) + ": line out of range");
+      for (int i = 0; i < NI; ++i)
+        for (int k2 = 0; k2 < R2; ++k2) A.check(what, N, SZ, O::z_v64(j, L), O::z_s64(i, k2), O::z_bytes);
+    }
+}
+
+template <typename T, int N>
+void audit_y(Audit& A) {
+  constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, NI = R1 / R2, H = R1 / 2;
+  constexpr int NLB = N * N / LPW;
+  constexpr uint32_t SZ = sizeof(C<T>);
+  using O = PadRaw<N, R1, R2, SZ>;
+  const size_t V = O::V;
+  A.check_resource("y column", N, O::y_bytes, 0, V, SZ);
+  // class (pz, px) base (pz * 4 + px) V of the 8 V transfer function, the
+  // largest base being class (1, 0, 1)
+  A.check_resource("transfer function", N, O::g_bytes, 5 * V, 8 * V, SZ);
+  // workgroup -> (system, class, line block) is a bijection for every batch
+  // size up to 40 (4 NLB is a multiple of 8)
+  if ((4 * NLB) % 8 != 0) A.fail("y pass: 4 N^2 / LPW not a multiple of 8");
+  for (int B = 1; B <= 40; ++B) {
+    std::vector<unsigned char> seen((size_t)4 * NLB * B, 0);
+    for (int h = 0; h < 4 * NLB * B; ++h) {
+      const YcSlot t = yc_slot(h, B, NLB);
+      if (t.b < 0 || t.b >= B || t.cls < 0 || t.cls >= 4 || t.lb < 0 || t.lb >= NLB) {
+        A.fail("y pass N=" + std::to_string(N) + " B=" + std::to_string(B) + ": workgroup outside the grid");
+        break;
+      }
+      unsigned char& c = seen[((size_t)t.b * 4 + t.cls) * NLB + t.lb];
+      if (c++) A.fail("y pass N=" + std::to_string(N) + " B=" + std::to_string(B) + ": slot taken twice");
+    }
+  }
+  for (int lb = 0; lb < NLB; ++lb)
+    for (int tid = 0; tid < RT; ++tid) {
+      const int L = lb * LPW + tid % LPW, j = tid / LPW;
+      const int kz = L / N, kx = L - kz * N;
+      for (int m = 0; m < H; ++m) A.check("y column", N, SZ, O::y_v64(kz, kx, j), O::y_s64(m), O::y_bytes);
+      for (int i = 0; i < NI; ++i)
+        for (int k2 = 0; k2 < R2; ++k2)
+          A.check("transfer function", N, SZ, O::g_v64(j, kz, kx), O::g_s64(i, k2), O::g_bytes);
+    }
+}
+
+template <typename T, int N>
+void audit_N(Audit& A) {
+  if constexpr (PadSel<T, N>::ok && N <= 128) {
+    audit_z<T, N, rtz<T, N>()>(A, "z lines");
+    if constexpr (zf_wide_ok<T, N>()) {
+      audit_z<T, N, 1024>(A, "z lines (1024-wide forward)");
+      audit_z<T, N, RT>(A, "z lines (256-wide forward)");
+    }
+  }
+  if constexpr (PadSel<T, N>::ok) audit_y<T, N>(A);
+}
+
+template <typename T>
+void audit_T(Audit& A) {
+  audit_N<T, 16>(A);
+  audit_N<T, 32>(A);
+  audit_N<T, 64>(A);
+  audit_N<T, 128>(A);
+  audit_N<T, 256>(A);
+}
+
+}  // namespace
+
 }  // namespace bq
+
+extern "C" int bq_audit_raw_ranges(char* report, int report_len, long long* accesses) {
+  bq::Audit A;
+  bq::audit_T<float>(A);
+  bq::audit_T<double>(A);
+  if (accesses) *accesses = A.accesses;
+  if (report && report_len > 0) {
+    const std::string m = A.bad ? A.msg : std::string("all raw buffer accesses in range");
+    std::snprintf(report, (size_t)report_len, "%s", m.c_str());
+  }
+  return A.bad;
+}

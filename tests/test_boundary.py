@@ -84,3 +84,18 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_raw_buffer_accesses_stay_in_range():
+    """Every offset the padded-line passes of G can form through a raw
+    buffer resource lies inside that resource, each resource is under 2^31
+    bytes and inside its allocation, and the y pass maps its workgroups one
+    to one onto (system, class, line block) for batches of 1..40 (host-side
+    enumeration over the launch grids of every built grid and precision)."""
+    from paper_2307_02043_amd import _lib as L
+    lib = L.load()
+    buf = ctypes.create_string_buffer(4096)
+    n = ctypes.c_longlong()
+    bad = lib.bq_audit_raw_ranges(buf, len(buf), ctypes.byref(n))
+    assert bad == 0, buf.value.decode()
+    assert n.value > 50_000_000  # every (thread, value) of every launch shape
