@@ -197,3 +197,35 @@ def test_256_prox_200_iterations_matches_stored_oracle(dev, prec):
     assert err < lim, err
     assert abs(float(torch.linalg.norm(x.double())) - float(ref["x_norm"])) < lim * float(ref["x_norm"])
     print(f"256^3 prox, 200 iterations, {prec}: sampled relative error {err:.2e}")
+
+
+C6 = syn.WORKLOADS["c6_ls128_strong"]
+
+
+def test_128_strong_scattering_f64_gradient_matches_stored_oracle(dev):
+    """The strongly scattering 128^3 workload (index up to 1.43) at the
+    phantom itself: about 55 BiCGSTAB iterations per solve at tol 1e-13.
+    FP64 gradient and loss of its first two illuminations against the
+    oracle's (1e-10 over 8192 stored voxels and on the norm), with the
+    oracle's iteration counts per illumination; the FP32 path at the
+    workload's tol 1e-6 within 2e-4."""
+    xt = syn.scattering_potential(syn.make_phantom(C6))
+    x = C6.x_eval_scale * xt
+    ref = _golden("c6_grad128_strong_b2.npz", ("oracle/green.py", "oracle/lsmodel.py"), x,
+                  syn.workload_directions(C6))
+    idx = [int(i) for i in ref["idx"]]
+    assert idx == [int(i) for i in syn.batch_indices(C6)[:2]]
+    sel = torch.from_numpy(ref["sel"]).to(dev)
+    for prec, tol, lim in (("f64", 1e-13, 1e-10), ("f32", 1e-6, 2e-4)):
+        rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+        ctx = _ctx(C6, prec, tol=tol, max_iter=1000)
+        g, f, info = ctx.grad(torch.from_numpy(x).to(dev, rd), torch.from_numpy(ref["y"]).to(dev, cd), idx, 0.5)
+        ctx.close()
+        assert info.status == 0
+        if prec == "f64":
+            assert info.iters_fwd == [int(s[0]) for s in ref["iters"]]
+            assert info.iters_adj == [int(s[1]) for s in ref["iters"]]
+        err = _rel(g.reshape(-1)[sel].double().cpu().numpy(), ref["g_sel"])
+        assert err < lim, (prec, err)
+        assert abs(float(torch.linalg.norm(g.double())) - float(ref["g_norm"])) < lim * float(ref["g_norm"])
+        assert abs(f - float(ref["loss"])) < lim * float(ref["loss"])
