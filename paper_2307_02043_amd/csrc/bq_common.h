@@ -473,6 +473,66 @@ __device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti) {
   dftR<T, true, R1>(d);
 }
 
+// Variants of line_fft_t / line_ifft_t for R1 = NI R2 > R2 whose exchange
+// passes through LDS in NI rounds, one per group i of NI: the line then
+// needs R2 rows of P slots instead of R1 (LineXS::LS), at one more barrier
+// pair per round.  Both directions read their twiddles from the forward
+// table alone (W^{(j + R2 i) jj} = tf[jj R1 + j + R2 i]), TW = R1 R2.
+template <int R1, int R2>
+struct LineXS {
+  static constexpr int P = R2 + 1;
+  static constexpr int LS = ((R2 - 1) * P + R2) | 1;
+  static constexpr int TW = R1 * R2;
+};
+
+template <typename T, int R1, int R2, bool INV>
+__device__ inline void line_fft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf) {
+  constexpr int NI = R1 / R2, P = LineXS<R1, R2>::P;
+  dftR<T, INV, R1>(d);
+  const C<T>* w = tf + j * R1;
+#pragma unroll
+  for (int k1 = 1; k1 < R1; ++k1) d[k1] = INV ? cmulc(d[k1], w[k1]) : cmul(d[k1], w[k1]);
+  C<T>* wp = line + j;
+  const C<T>* rp = line + j * P;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    // values k1 = R2 i + kk of every thread to slot (kk, thread); thread j
+    // then reads its column k1 = j + R2 i over all threads into the same
+    // registers (their values are in LDS by then)
+#pragma unroll
+    for (int kk = 0; kk < R2; ++kk) wp[kk * P] = d[i * R2 + kk];
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < R2; ++jj) d[i * R2 + jj] = rp[jj];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) dftR<T, INV, R2>(&d[i * R2]);
+}
+
+template <typename T, int R1, int R2>
+__device__ inline void line_ifft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf) {
+  constexpr int NI = R1 / R2, P = LineXS<R1, R2>::P;
+  C<T>* wp = line + j * P;
+  const C<T>* rp = line + j;
+  const C<T>* w = tf + j;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    dftR<T, true, R2>(&d[i * R2]);
+#pragma unroll
+    for (int jj = 0; jj < R2; ++jj) {
+      C<T> v = d[i * R2 + jj];
+      if (jj) v = cmulc(v, w[jj * R1 + R2 * i]);
+      wp[jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < R2; ++kk) d[i * R2 + kk] = rp[kk * P];
+    __syncthreads();
+  }
+  dftR<T, true, R1>(d);
+}
+
 // ---------------------------------------------------------------------------
 // Row-wise traversal of an image with nrows rows (z, y) of nx points: rows
 // over workgroups, x over threads.  When a row is shorter than the

@@ -366,14 +366,16 @@ struct PadSel {
 
 // Twiddle tables of line_fft_t / line_ifft_t for the padded 2N-point lines:
 // W_{2N}^n = exp(-i pi n / N) from the half-angle table (n < 2N).
-template <typename T, int N, int R1, int R2, int NTH = RT>
+// INV_ROWS: also the inverse table (rows of k1) after the forward one; the
+// split-exchange transforms read both directions from the forward table.
+template <typename T, int N, int R1, int R2, int NTH = RT, bool INV_ROWS = true>
 __device__ inline void load_twtab_pad(C<T>* t, const C<T>* twH, int tid) {
   for (int e = tid; e < R1 * R2; e += NTH) {
     const int a = e / R1, b = e - a * R1, n = a * b;
     const C<T> w = twH[n < N ? n : n - N];
     const C<T> v = n < N ? w : C<T>{-w.x, -w.y};
     t[e] = v;
-    if constexpr (R1 != R2) t[R1 * R2 + b * R2 + a] = v;
+    if constexpr (R1 != R2 && INV_ROWS) t[R1 * R2 + b * R2 + a] = v;
   }
 }
 
@@ -424,10 +426,15 @@ __global__ void __launch_bounds__(NTH) k_zf_p(PassArgs<T> a) {
 template <typename T, int N>
 __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = RT / R2, NI = R1 / R2;
-  constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;
+  // R1 > R2 (the 512-point lines at N = 256): the exchange runs in NI rounds
+  // through an LDS line of R2 rows, so that 4 workgroups fit a CU (2 with
+  // the whole line: 76 KB each)
+  constexpr bool SPLIT = R1 != R2;
+  constexpr int LS = SPLIT ? LineXS<R1, R2>::LS : LineX<R1, R2>::LS, H = R1 / 2;
+  constexpr int TW = SPLIT ? LineXS<R1, R2>::TW : LineX<R1, R2>::TW;
   constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> twt[LineX<R1, R2>::TW];
+  __shared__ C<T> twt[TW];
   // XCD-aware order: workgroup h runs on XCD h mod 8; the B systems of one
   // (class, line block) take consecutive slots of the same XCD, so the
   // transfer-function slab they share is fetched into that XCD's L2 once.
@@ -436,7 +443,7 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   const int b = slot.b, cls = slot.cls, lb = slot.lb, pz = cls >> 1, px = cls & 1;
   const int tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_twtab_pad<T, N, R1, R2>(twt, a.twH, tid);
+  load_twtab_pad<T, N, R1, R2, RT, !SPLIT>(twt, a.twH, tid);
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = lb * LPW + line;
   const int kz = L / N, kx = L - kz * N;
@@ -452,13 +459,19 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   const brsrc rg = make_rsrc(a.ghat + (size_t)(pz * 4 + px) * V, O::g_bytes);
   const uint32_t vg = O::g_v(j, kz, kx);
   __syncthreads();
-  line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
+  if constexpr (SPLIT)
+    line_fft_ts<T, R1, R2, false>(d, &lds[line * LS], j, twt);
+  else
+    line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
       d[i * R2 + k2] = cmul(d[i * R2 + k2], bload<T>(rg, vg, O::g_s(i, k2)));
-  line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
+  if constexpr (SPLIT)
+    line_ifft_ts<T, R1, R2>(d, &lds[line * LS], j, twt);
+  else
+    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, twt);
 #pragma unroll
   for (int m = 0; m < H; ++m) bstore<T, true>(d[m], rc, vo, O::y_s(m));
 }
