@@ -16,6 +16,9 @@ Contents (each function cites the passage of arXiv:2307.02043 it follows):
 * tvprox     -- discrete TV, its dual, the weighted projection onto the
                 nonnegative orthant under tau I + U U^T (Theorem 3.1) and the
                 fast dual projected gradient iteration of Section 4.1.
+* camera     -- camera sampling of the detector-plane field (an M x M camera
+                of its own pitch: trigonometric interpolation of the window's
+                field) and its adjoint; a model class that adds it to lsmodel.
 * bqnpm      -- the SR1 metric of Algorithm 4.2 and the outer iteration of
                 Algorithm 4.1 over the two above.
 
@@ -24,4 +27,4 @@ closed form, a brute-force or dense computation, or an invariant; the paper
 prints no worked example for this path, so agreement with its printed
 figures is "parity unpinned" (its phantoms and data are not available).
 """
-from . import green, lsmodel, tvprox  # noqa: F401
+from . import camera, green, lsmodel, tvprox  # noqa: F401
