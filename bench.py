@@ -476,32 +476,42 @@ def cpu_baseline(w, xt, dirs, idx, mean_iters, iters_all, iters_1t):
     return out
 
 
-def bench_detprop(w, dev, xt, dirs, idx, scale, steps, base_ms, d_um=1.0):
+def bench_detprop(w, dev, xt, dirs, idx, scale, steps, base_ms, d_um=1.0, cam_n=512):
     """The batched FP32 gradient of the workload with the detector plane
     d_um beyond the exit plane (angular-spectrum propagation before the
-    residual and its adjoint before the adjoint right-hand side)."""
+    residual and its adjoint before the adjoint right-hand side), and the
+    same with a cam_n x cam_n camera sampling that plane over the window
+    (pitch N h / cam_n, as a 512^2 camera over the paper's field of view)."""
     import torch
 
     from paper_2307_02043_amd import LSContext
 
-    ctx = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=1e-6, max_iter=w.max_iter,
-                    det_dist_um=d_um)
-    xtt = torch.from_numpy(xt).to(dev, torch.float32)
-    y = ctx.forward(xtt, idx)[0]
-    ctx.close()
-    ctx = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol, max_iter=w.max_iter,
-                    det_dist_um=d_um)
-    x = (0.5 * xtt).contiguous()
-    ctx.grad(x, y, idx, scale)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
+    out = {"det_dist_um": d_um, "exit_plane_ms_per_step": round(base_ms, 3)}
+    pitch = w.N * w.h_um / cam_n
+    for key, cam in (("ms_per_step", {}), ("camera", {"cam_n": cam_n, "cam_pitch_um": pitch})):
+        ctx = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=1e-6, max_iter=w.max_iter,
+                        det_dist_um=d_um, **cam)
+        xtt = torch.from_numpy(xt).to(dev, torch.float32)
+        y = ctx.forward(xtt, idx)[0]
+        ctx.close()
+        ctx = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", "ls", tol=w.tol, max_iter=w.max_iter,
+                        det_dist_um=d_um, **cam)
+        x = (w.x_eval_scale * xtt).contiguous()
         ctx.grad(x, y, idx, scale)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t) / steps * 1e3
-    ctx.close()
-    log(f"detector plane {d_um} um beyond the exit plane: {ms:.2f} ms per gradient step")
-    return {"det_dist_um": d_um, "ms_per_step": round(ms, 3), "exit_plane_ms_per_step": round(base_ms, 3)}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.grad(x, y, idx, scale)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / steps * 1e3
+        ctx.close()
+        if cam:
+            out["camera"] = {"pixels": cam_n, "pitch_um": round(pitch, 6), "ms_per_step": round(ms, 3)}
+            log(f"camera {cam_n}^2 (pitch {pitch:.4f} um) on that plane: {ms:.2f} ms per gradient step")
+        else:
+            out["ms_per_step"] = round(ms, 3)
+            log(f"detector plane {d_um} um beyond the exit plane: {ms:.2f} ms per gradient step")
+    return out
 
 
 def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):

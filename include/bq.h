@@ -89,6 +89,21 @@ typedef struct {
                          the N x N window, is propagated by the angular
                          spectrum exp(i k_z d) (evanescent parts decaying);
                          the adjoint uses the conjugate transfer function  */
+  int cam_n;          /* camera pixels per side M (0 <= M <= 4096).  0: the
+                         detector images are the N x N lateral window.  > 0:
+                         an M x M camera centred on the optical axis samples
+                         the detector-plane field (after the propagation
+                         above) at its pixel centres (a - (M-1)/2) pitch, by
+                         trigonometric interpolation of the window's samples
+                         (the field taken as periodic over the window and
+                         band limited to its DFT frequencies, the Nyquist bin
+                         of an even N at -pi/h).  Images, measurements y and
+                         residuals are then M x M; the adjoint right-hand
+                         side uses the adjoint sampling.  The paper's cameras
+                         (512^2, 150^2 pixels, Section 6) have their own pixel
+                         count and pitch; their optics are not given      */
+  double cam_pitch_um; /* camera pixel pitch in the sample plane (um, > 0 when
+                          cam_n > 0)                                        */
 } bq_geom;
 
 /* Unit propagation direction of a plane-wave illumination
@@ -131,8 +146,9 @@ const char* bq_last_error(const bq_ctx* ctx);
  * Lippmann-Schwinger solve per illumination; first Born: S G(x u_in)).
  *   x      device, N^3 real potential
  *   idx    host, B indices in [0, L)
- *   y_out  device, B x N x N complex: the scattered field S(u_l - u_in,l) on
- *          the detector plane z = N-1
+ *   y_out  device, B x D x D complex (D = cam_n, or N without a camera): the
+ *          scattered field S(u_l - u_in,l) on the detector plane z = N-1,
+ *          propagated and sampled by the camera as set in bq_geom
  *   st     host, B entries or NULL */
 bq_status bq_forward(bq_ctx* ctx, const void* x, const int* idx, int B, void* y_out,
                      bq_solve_stats* st);
@@ -146,9 +162,11 @@ bq_status bq_fields(bq_ctx* ctx, const void* x, const int* idx, int B, void* u_o
  * S/L passed explicitly):
  *   g_out = scale * sum_b Re(conj(u_b) . w_b),
  *   (I - G^H diag(x)) w_b = G^H S^T r_b,  r_b = S(u_b - u_in,b) - y_b,
- *   *loss = scale * sum_b 1/2 ||r_b||^2.
+ *   *loss = scale * sum_b 1/2 ||r_b||^2
+ *   (S including the propagation and the camera when set in bq_geom).
  *   x      device, N^3 real
- *   y      device, B x N x N complex, y[b] measured for illumination idx[b]
+ *   y      device, B x D x D complex (D as for bq_forward), y[b] measured
+ *          for illumination idx[b]
  *   g_out  device, N^3 real, overwritten
  *   loss   host, may be NULL
  *   st     host, B entries or NULL */

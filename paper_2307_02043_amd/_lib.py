@@ -36,7 +36,7 @@ class Geom(ct.Structure):
     _fields_ = [("N", ct.c_int), ("h_um", ct.c_double), ("lambda0_um", ct.c_double),
                 ("n_b", ct.c_double), ("precision", ct.c_int), ("model", ct.c_int),
                 ("tol", ct.c_double), ("max_iter", ct.c_int), ("flags", ct.c_uint),
-                ("det_dist_um", ct.c_double)]
+                ("det_dist_um", ct.c_double), ("cam_n", ct.c_int), ("cam_pitch_um", ct.c_double)]
 
 
 class Illum(ct.Structure):

@@ -62,9 +62,12 @@ class LSContext:
                  directions, precision: str = "f32", model: str = "ls",
                  tol: float = 1e-5, max_iter: int = 300, plain: bool = False,
                  fused_xy: bool = False, stream: torch.cuda.Stream | None = None,
-                 det_dist_um: float = 0.0, graphs: bool = False):
+                 det_dist_um: float = 0.0, graphs: bool = False, cam_n: int = 0,
+                 cam_pitch_um: float = 0.0):
         """graphs=True replays one captured BiCGSTAB iteration as a HIP graph
-        instead of launching its kernels one by one (same results)."""
+        instead of launching its kernels one by one (same results).
+        cam_n > 0: detector images are taken by a cam_n x cam_n camera of
+        pitch cam_pitch_um (um) centred on the axis."""
         self._lib = L.load()
         self.N = int(N)
         self.precision = precision
@@ -79,7 +82,8 @@ class LSContext:
                    float(tol), int(max_iter),
                    (L.BQ_FLAG_PLAIN if plain else 0) | (L.BQ_FLAG_FUSED_XY if fused_xy else 0)
                    | (L.BQ_FLAG_GRAPH if graphs else 0),
-                   float(det_dist_um))
+                   float(det_dist_um), int(cam_n), float(cam_pitch_um))
+        self.ndet = int(cam_n) if cam_n > 0 else self.N
         ill = (L.Illum * self.L)(*[L.Illum(*row) for row in d])
         self._stream = stream
         h = ct.c_void_p()
@@ -161,7 +165,8 @@ class LSContext:
         N = self.N
         x = self._real(x, (N, N, N))
         a, pidx, B = self._idx(idx)
-        y = torch.empty((B, N, N), dtype=self.cdtype, device=x.device)
+        D = self.ndet
+        y = torch.empty((B, D, D), dtype=self.cdtype, device=x.device)
         st = (L.SolveStats * B)()
         s = self._check(self._lib.bq_forward(self._h, _ptr(x), pidx, B, _ptr(y), st))
         return y, _stats(st, B, s)
@@ -180,7 +185,7 @@ class LSContext:
         N = self.N
         x = self._real(x, (N, N, N))
         a, pidx, B = self._idx(idx)
-        y = self._cplx(y, (B, N, N))
+        y = self._cplx(y, (B, self.ndet, self.ndet))
         g = self._out(out, (N, N, N))
         loss = ct.c_double(0.0)
         st = (L.SolveStats * B)()
@@ -195,7 +200,7 @@ class LSContext:
         N = self.N
         x = self._real(x, (N, N, N))
         a, pidx, B = self._idx(idx)
-        y = self._cplx(y, (B, N, N))
+        y = self._cplx(y, (B, self.ndet, self.ndet))
         for f in (u, w):
             if f.dtype != self.cdtype or tuple(f.shape) != (B, N, N, N) or not f.is_contiguous():
                 raise ValueError("u, w must be contiguous (B, N, N, N) tensors of the context's complex type")
@@ -210,7 +215,7 @@ class LSContext:
         N = self.N
         x = self._real(x, (N, N, N))
         a, pidx, B = self._idx(idx)
-        y = self._cplx(y, (B, N, N))
+        y = self._cplx(y, (B, self.ndet, self.ndet))
         loss = ct.c_double(0.0)
         st = (L.SolveStats * B)()
         s = self._check(self._lib.bq_loss(self._h, _ptr(x), _ptr(y), pidx, B, float(scale),
@@ -390,8 +395,9 @@ class QNIteration:
         N = self._ls.N
         if x.dtype != self._ls.rdtype or tuple(x.shape) != (N, N, N) or not x.is_contiguous():
             raise ValueError("x must be a contiguous N^3 tensor of the context's real type")
-        if y.dtype != self._ls.cdtype or tuple(y.shape) != (self._ls.L, N, N):
-            raise ValueError("y must be (L, N, N) of the context's complex type")
+        D = self._ls.ndet
+        if y.dtype != self._ls.cdtype or tuple(y.shape) != (self._ls.L, D, D):
+            raise ValueError("y must be (L, D, D) of the context's complex type (D: detector pixels per side)")
         y = y.contiguous()
         info = L.QnInfo()
         s = self._lib.bq_qn_step(self._h, _ptr(x), _ptr(y), int(pick), ct.byref(info))

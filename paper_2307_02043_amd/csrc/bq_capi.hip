@@ -66,7 +66,7 @@ void drop_graphs(bq_ctx* c) {
 void free_batch(bq_ctx* c) {
   drop_graphs(c);
   for (auto& p : c->f) { if (p) (void)hipFree(p); p = nullptr; }
-  void** others[] = {&c->zh, &c->xh, &c->rdet, (void**)&c->inc, (void**)&c->state,
+  void** others[] = {&c->zh, &c->xh, &c->rdet, &c->camwin, &c->camtmp, (void**)&c->inc, (void**)&c->state,
                      (void**)&c->part_mv, (void**)&c->part_vec, (void**)&c->part_det};
   for (void** p : others) { if (*p) (void)hipFree(*p); *p = nullptr; }
   void** pinned[] = {(void**)&c->hstate, (void**)&c->hinc, (void**)&c->hpart};
@@ -77,7 +77,9 @@ void free_batch(bq_ctx* c) {
 // Device bytes of the batch workspace per system (see ensure_capacity).
 size_t per_system_bytes(const bq_ctx* c) {
   const size_t N = (size_t)c->g.N;
-  return (8 + 2 + 4) * c->V * c->csz + N * N * c->csz + 3 * N * sizeof(C<double>) + sizeof(SysState) +
+  const size_t M = (size_t)c->ndet;
+  const size_t cam = c->camD ? (N * N + N * M) * c->csz : 0;
+  return (8 + 2 + 4) * c->V * c->csz + M * M * c->csz + cam + 3 * N * sizeof(C<double>) + sizeof(SysState) +
          ((size_t)c->np_mv + (size_t)c->np_vec) * 4 * sizeof(double) + (size_t)c->np_det * sizeof(double);
 }
 
@@ -111,7 +113,9 @@ bq_status ensure_capacity(bq_ctx* c, int B) {
   for (auto& p : c->f)
     if (hipMalloc(&p, fb) != hipSuccess) { free_batch(c); return set_err(c, BQ_ENOMEM, "out of device memory (fields)"); }
   if (hipMalloc(&c->zh, 2 * fb) != hipSuccess || hipMalloc(&c->xh, 4 * fb) != hipSuccess ||
-      hipMalloc(&c->rdet, (size_t)B * c->g.N * c->g.N * c->csz) != hipSuccess ||
+      hipMalloc(&c->rdet, (size_t)B * c->ndet * c->ndet * c->csz) != hipSuccess ||
+      (c->camD && (hipMalloc(&c->camwin, (size_t)B * c->g.N * c->g.N * c->csz) != hipSuccess ||
+                   hipMalloc(&c->camtmp, (size_t)B * c->g.N * c->ndet * c->csz) != hipSuccess)) ||
       hipMalloc((void**)&c->inc, (size_t)B * 3 * c->g.N * sizeof(C<double>)) != hipSuccess ||
       hipMalloc((void**)&c->state, (size_t)B * sizeof(SysState)) != hipSuccess ||
       hipMalloc((void**)&c->part_mv, (size_t)B * c->np_mv * 4 * sizeof(double)) != hipSuccess ||
@@ -202,26 +206,37 @@ bq_status check_launch(bq_ctx* c, const char* where) {
   return BQ_OK;
 }
 
-// Detector images of nb systems: out = P S(field - sub u_in), and with y
+// Detector images of nb systems: out = C P S(field - sub u_in), and with y
 // given r = out - y with the loss partials; P = identity, or the angular-
-// spectrum propagation to the detector plane when det_dist_um > 0.
+// spectrum propagation to the detector plane when det_dist_um > 0; C =
+// identity, or the camera sampling (ndet x ndet pixels) when cam_n > 0.
 template <typename T>
 void det_images(bq_ctx* c, int nb, const C<T>* field, int sub, const C<T>* y, C<T>* out, double* part) {
-  const int N = c->g.N;
-  if (!c->dettab) {
+  const int N = c->g.N, M = c->ndet;
+  if (!c->dettab && !c->camD) {
     detector<T>(nb, N, field, sub, c->inc, y, out, part, c->np_det, c->stream);
     return;
   }
-  detector<T>(nb, N, field, sub, c->inc, nullptr, out, nullptr, c->np_det, c->stream);
-  plane_propagate<T>(nb, N, out, (const C<T>*)c->twN, (const C<T>*)c->dettab, 0, c->stream);
-  if (y) det_residual<T>(nb, N, out, y, part, c->np_det, c->stream);
+  C<T>* win = c->camD ? (C<T>*)c->camwin : out;
+  detector<T>(nb, N, field, sub, c->inc, nullptr, win, nullptr, c->np_det, c->stream);
+  if (c->dettab) plane_propagate<T>(nb, N, win, (const C<T>*)c->twN, (const C<T>*)c->dettab, 0, c->stream);
+  if (c->camD) camera_apply<T>(nb, N, M, win, (const C<T>*)c->camD, (C<T>*)c->camtmp, out, c->stream);
+  if (y) det_residual<T>(nb, M, out, y, part, c->np_det, c->stream);
 }
 
-// P^H applied to the residual images before the adjoint right-hand side
+// C^H and P^H applied to the residual images (rdet, ndet x ndet) before the
+// adjoint right-hand side; returns the N x N window images it reads.
 template <typename T>
-void det_adjoint(bq_ctx* c, int nb) {
+const C<T>* det_adjoint(bq_ctx* c, int nb) {
+  C<T>* win = (C<T>*)c->rdet;
+  if (c->camD) {
+    win = (C<T>*)c->camwin;
+    camera_adjoint<T>(nb, c->g.N, c->ndet, (const C<T>*)c->rdet, (const C<T>*)c->camD, (C<T>*)c->camtmp, win,
+                      c->stream);
+  }
   if (c->dettab)
-    plane_propagate<T>(nb, c->g.N, (C<T>*)c->rdet, (const C<T>*)c->twN, (const C<T>*)c->dettab, 1, c->stream);
+    plane_propagate<T>(nb, c->g.N, win, (const C<T>*)c->twN, (const C<T>*)c->dettab, 1, c->stream);
+  return win;
 }
 
 // The captured iteration of a batched solve with these operands (captured on
@@ -456,7 +471,7 @@ bq_status do_forward(bq_ctx* c, const void* x, const int* idx, int B, void* out,
   if (bq_status s = ensure_capacity(c, step)) return s;
   std::vector<bq_solve_stats> stats(B);
   const int N = c->g.N;
-  const size_t N2 = (size_t)N * N;
+  const size_t N2 = (size_t)c->ndet * c->ndet;  // detector pixels per image
   for (int b0 = 0; b0 < B; b0 += step) {
     const int nb = std::min(step, B - b0);
     if (bq_status s = upload_incident(c, idx + b0, nb)) return s;
@@ -498,7 +513,7 @@ bq_status do_loss(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   if (bq_status s = ensure_capacity(c, step)) return s;
   std::vector<bq_solve_stats> stats(B);
   const int N = c->g.N;
-  const size_t N2 = (size_t)N * N;
+  const size_t N2 = (size_t)c->ndet * c->ndet;  // detector pixels per image
   const bool born = c->g.model == BQ_MODEL_BORN;
   double total = 0.0;
   for (int b0 = 0; b0 < B; b0 += step) {
@@ -553,7 +568,7 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
   if (bq_status s = ensure_capacity(c, step)) return s;
   std::vector<bq_solve_stats> stats(B);
   const int N = c->g.N;
-  const size_t N2 = (size_t)N * N;
+  const size_t N2 = (size_t)c->ndet * c->ndet;  // detector pixels per image
   const bool born = c->g.model == BQ_MODEL_BORN;
   double total_loss = 0.0;
   for (int b0 = 0; b0 < B; b0 += step) {
@@ -580,7 +595,7 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
     }
     record(c, stats, b0, nb, true, 1);
     det_images<T>(c, nb, field, sub, (const C<T>*)y + (size_t)b0 * N2, (C<T>*)c->rdet, c->part_det);
-    det_adjoint<T>(c, nb);
+    const C<T>* rwin = det_adjoint<T>(c, nb);
     // adjoint right-hand side (conjugated): G S^T conj(P^H r); for a warm start
     // it goes to the p buffer (free until the first iteration) and the solve
     // starts from w_io
@@ -588,7 +603,7 @@ bq_status do_grad(bq_ctx* c, const void* x, const void* y, const int* idx, int B
     void* we = ws ? (void*)((C<T>*)w_io + (size_t)b0 * c->V) : c->f[F_W];
     {
       PassArgs<T> a = pass_args<T>(c, nb, c->inc);
-      a.rdet = (const C<T>*)c->rdet;
+      a.rdet = rwin;
       a.zf_mode = ZF_DETCONJ;
       a.zi_mode = ZI_G;
       a.out = warm_adj ? (C<T>*)c->f[F_P] : (C<T>*)we;
@@ -672,6 +687,47 @@ bq_status create_tables(bq_ctx* c) {
       }
     HIPCHK(c, hipMalloc(&c->dettab, (size_t)N * N * sizeof(C<T>)));
     HIPCHK(c, hipMemcpy(c->dettab, tf.data(), (size_t)N * N * sizeof(C<T>), hipMemcpyHostToDevice));
+  }
+  if (c->g.cam_n > 0) {
+    // camera: D[a][n] = (1/N) sum_m exp(i k_m (c_a - x_n)), the trigonometric
+    // interpolation of the window's samples x_n at the pixel centres c_a,
+    // k_m the window's DFT frequencies (signed, -pi/h for the Nyquist bin),
+    // formed as (1/N) Ec Ex^H in long double
+    const int M = c->g.cam_n;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double h = (long double)c->g.h_um, p = (long double)c->g.cam_pitch_um;
+    const long double dk = 2.0L * pi / ((long double)N * h);
+    std::vector<long double> km(N);
+    for (int m = 0; m < N; ++m) km[m] = dk * (m < N / 2 ? m : m - N);
+    std::vector<long double> ecr((size_t)M * N), eci((size_t)M * N), exr((size_t)N * N), exi((size_t)N * N);
+    for (int a = 0; a < M; ++a) {
+      const long double ca = ((long double)a - 0.5L * (M - 1)) * p;
+      for (int m = 0; m < N; ++m) {
+        ecr[(size_t)a * N + m] = cosl(km[m] * ca);
+        eci[(size_t)a * N + m] = sinl(km[m] * ca);
+      }
+    }
+    for (int n = 0; n < N; ++n) {
+      const long double xn = ((long double)n - 0.5L * (N - 1)) * h;
+      for (int m = 0; m < N; ++m) {
+        exr[(size_t)n * N + m] = cosl(km[m] * xn);
+        exi[(size_t)n * N + m] = sinl(km[m] * xn);
+      }
+    }
+    std::vector<C<T>> D((size_t)M * N);
+    for (int a = 0; a < M; ++a)
+      for (int n = 0; n < N; ++n) {
+        long double re = 0, im = 0;
+        for (int m = 0; m < N; ++m) {  // Ec[a][m] conj(Ex[n][m])
+          const long double pr = ecr[(size_t)a * N + m], pi_ = eci[(size_t)a * N + m];
+          const long double qr = exr[(size_t)n * N + m], qi = exi[(size_t)n * N + m];
+          re += pr * qr + pi_ * qi;
+          im += pi_ * qr - pr * qi;
+        }
+        D[(size_t)a * N + n] = C<T>{(T)(re / N), (T)(im / N)};
+      }
+    HIPCHK(c, hipMalloc(&c->camD, D.size() * sizeof(C<T>)));
+    HIPCHK(c, hipMemcpy(c->camD, D.data(), D.size() * sizeof(C<T>), hipMemcpyHostToDevice));
   }
   if (hipMalloc(&c->ghat, 8 * c->V * sizeof(C<T>)) != hipSuccess)
     return set_err(c, BQ_ENOMEM, "out of device memory (transfer function)");
@@ -782,6 +838,7 @@ void destroy_ctx(bq_ctx* c) {
   if (c->twN) (void)hipFree(c->twN);
   if (c->twH) (void)hipFree(c->twH);
   if (c->dettab) (void)hipFree(c->dettab);
+  if (c->camD) (void)hipFree(c->camD);
   delete c;
 }
 
@@ -798,6 +855,8 @@ bq_status bq_create(const bq_geom* g, const bq_illum* dirs, int L, void* stream,
     return set_err(nullptr, BQ_EINVAL, "h, lambda0, n_b must be > 0; tol, max_iter >= 0");
   if (!(g->det_dist_um >= 0) || !std::isfinite(g->det_dist_um))
     return set_err(nullptr, BQ_EINVAL, "det_dist_um must be finite and >= 0");
+  if (g->cam_n < 0 || g->cam_n > 4096 || (g->cam_n > 0 && !(g->cam_pitch_um > 0 && std::isfinite(g->cam_pitch_um))))
+    return set_err(nullptr, BQ_EINVAL, "cam_n must be in [0, 4096], with a finite cam_pitch_um > 0 when > 0");
   if (g->precision != BQ_F32 && g->precision != BQ_F64) return set_err(nullptr, BQ_EINVAL, "precision");
   if (g->model != BQ_MODEL_LS && g->model != BQ_MODEL_BORN) return set_err(nullptr, BQ_EINVAL, "model");
   for (int l = 0; l < L; ++l) {
@@ -816,7 +875,8 @@ bq_status bq_create(const bq_geom* g, const bq_illum* dirs, int L, void* stream,
   c->V = (size_t)g->N * g->N * g->N;
   c->csz = g->precision == BQ_F32 ? sizeof(C<float>) : sizeof(C<double>);
   c->np_vec = vec_num_partials(c->V);
-  c->np_det = det_num_partials(g->N);
+  c->ndet = g->cam_n > 0 ? g->cam_n : g->N;
+  c->np_det = det_num_partials(c->ndet);
   bq_status s = g->precision == BQ_F32 ? create_tables<float>(c) : create_tables<double>(c);
   if (s != BQ_OK) {
     g_create_error = c->err;

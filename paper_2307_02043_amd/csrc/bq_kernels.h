@@ -85,6 +85,11 @@ template <typename T> int xy_fused_launch(const PassArgs<T>& a, hipStream_t st);
 template <typename T> int ghat_precompute(int N, double h, double kb, C<T>* out, hipStream_t st);
 template <typename T>
 int plane_propagate(int B, int N, C<T>* planes, const C<T>* twN, const C<T>* tf, int adjoint, hipStream_t st);
+// camera sampling D f D^T of B window images (N x N) into M x M, and its adjoint
+template <typename T>
+void camera_apply(int B, int N, int M, const C<T>* win, const C<T>* D, C<T>* tmp, C<T>* out, hipStream_t st);
+template <typename T>
+void camera_adjoint(int B, int N, int M, const C<T>* r, const C<T>* D, C<T>* tmp, C<T>* win, hipStream_t st);
 int ghat_oversampling(int N);
 
 // ---- BiCGSTAB and the data term -------------------------------------------

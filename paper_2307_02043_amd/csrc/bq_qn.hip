@@ -275,7 +275,7 @@ bq_status qn_step(bq_qn* q, void* xv, const void* y, int pick, bq_qn_info* info)
   T* g = (T*)q->g;
   T* v = (T*)q->v;
   // measurements of the subset, gathered in its index order
-  const size_t row = (size_t)q->N * q->N * q->csz;
+  const size_t row = (size_t)q->ls->ndet * q->ls->ndet * q->csz;
   for (int i = 0; i < q->len[sp]; ++i)
     if (hipMemcpyAsync((char*)q->ybuf + i * row, (const char*)y + (size_t)q->idx[q->off[sp] + i] * row, row,
                        hipMemcpyDeviceToDevice, q->stream) != hipSuccess)
@@ -442,7 +442,7 @@ bq_status bq_qn_create(bq_ctx* ls, bq_prox* px, const bq_qn_params* prm, const i
       hipMalloc(&q->U, p.S * img) != hipSuccess || hipMalloc(&q->Uc, p.S * img) != hipSuccess ||
       hipMalloc(&q->g, img) != hipSuccess ||
       hipMalloc(&q->v, img) != hipSuccess ||
-      hipMalloc(&q->ybuf, (size_t)q->maxlen * N * N * q->csz) != hipSuccess ||
+      hipMalloc(&q->ybuf, (size_t)q->maxlen * ls->ndet * ls->ndet * q->csz) != hipSuccess ||
       hipMalloc((void**)&q->part, (size_t)q->np * QN_K * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&q->res, QN_K * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&q->hres, QN_K * sizeof(double)) != hipSuccess ||

@@ -26,6 +26,11 @@ struct bq_ctx {
   void* twN = nullptr;
   void* twH = nullptr;
   void* dettab = nullptr;  // detector transfer function / N^2 (N x N, [ky][kx]) when det_dist_um > 0
+  // camera (cam_n > 0): ndet = cam_n pixels per side, else the N x N window
+  int ndet = 0;
+  void* camD = nullptr;    // M x N trigonometric interpolation matrix (camera)
+  void* camwin = nullptr;  // B window images (N x N) between the field and the camera
+  void* camtmp = nullptr;  // B intermediate products (N x M)
   void* f[8] = {};  // u w r rhat p v s t
   void* zh = nullptr;
   void* xh = nullptr;
