@@ -190,7 +190,17 @@ bq_status qn_pair(bq_qn* q, const T* x, const T* xb, const T* g, const T* gb, do
   return qn_reduce(q, mode == 0 ? 3 : 2);
 }
 
-// Algorithm 4.2 for subset sp from the pair (x - xbar, g - gbar)
+// SR1 metric tau I + u u^T of subset sp (Algorithm 4.2) from its pair
+// s = x - xbar, m = g - gbar.  Along r(tau) = m - tau s the curvature
+// <r, s> = <m, s> - tau <s, s> is linear in tau and <r, r> = <m, m> -
+// 2 tau <m, s> + tau^2 <s, s>, so after the three inner products of the
+// pair (and <r, s>, <r, r> at the first tau, reduced from the vectors) the
+// halvings of tau that the curvature condition <r, s> > delta2 <s, s> asks
+// for are found on the host from the closed form, with no further pass
+// over the images.  The kept correction u = r / sqrt(<r, s>) is normalised
+// by <r, s> reduced once more at the final tau; should that exact value
+// still fail the condition (the closed form having cancelled), the halving
+// goes on with reduced values.
 template <typename T>
 bq_status qn_sr1(bq_qn* q, int sp, const T* x, const T* g) {
   const size_t V = q->V;
@@ -201,28 +211,36 @@ bq_status qn_sr1(bq_qn* q, int sp, const T* x, const T* g) {
   const double mm = q->hres[0], sm = q->hres[1], ss = q->hres[2];
   if (!(ss > 0.0)) return BQ_OK;  // same iterate as the stored pair: keep the metric
   const double alpha = q->prm.alpha;
-  double tau = mm / (q->prm.gamma * sm);
-  tau = std::fmin(tau, q->prm.tau_max);
+  double tau = std::fmin(mm / (q->prm.gamma * sm), q->prm.tau_max);
   bool keep = false;
   if (!(tau > 0.0)) {
     tau = alpha;
   } else {
     if (bq_status s = qn_pair<T>(q, x, xb, g, gb, tau, 1)) return s;
-    double rs = q->hres[0];
-    const double rr = q->hres[1];
-    if (rs <= QN_DELTA1 * std::sqrt(ss) * std::sqrt(rr)) {
-      keep = false;
-    } else {
+    const double rs0 = q->hres[0], rr0 = q->hres[1];
+    // a correction whose curvature is negligible against |r| |s| is
+    // dropped (tau kept); otherwise halve tau until <r, s> > delta2 <s, s>
+    if (rs0 > QN_DELTA1 * std::sqrt(ss) * std::sqrt(rr0)) {
       keep = true;
-      while (rs <= QN_DELTA2 * ss) {
-        if (tau < QN_DELTA2) {
+      const double tau0 = tau;
+      double rs = rs0;
+      bool exact = true;  // rs reduced from the vectors at this tau
+      for (;;) {
+        if (rs > QN_DELTA2 * ss) {
+          if (exact) break;
+          if (bq_status s = qn_pair<T>(q, x, xb, g, gb, tau, 1)) return s;
+          rs = q->hres[0];
+          exact = true;
+          continue;
+        }
+        if (tau < QN_DELTA2) {  // no usable curvature along r
           tau = alpha;
           keep = false;
           break;
         }
-        tau = tau / 2.0;
-        if (bq_status s = qn_pair<T>(q, x, xb, g, gb, tau, 1)) return s;
-        rs = q->hres[0];
+        tau *= 0.5;
+        rs = rs0 + (tau0 - tau) * ss;  // <m - tau s, s> from its value at tau0
+        exact = false;
       }
       if (keep)
         hipLaunchKernelGGL((k_qn_ucol<T>), dim3(q->np), dim3(QN_WG), 0, q->stream, x, xb, g, gb, V, tau,
