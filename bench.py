@@ -90,7 +90,8 @@ def copy_calibration(dev, mib):
     del src, dst
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ls_grad_128cubed_b16_f32_hbm_traffic.txt")
+TRAFFIC_FILES = (os.path.join(ROOT, "profiles", "ls_grad_128cubed_b16_f32_hbm_traffic.txt"),
+                 os.path.join(ROOT, "profiles", "ls_grad_256cubed_b32_f32_hbm_traffic.txt"))
 
 
 # sources that define the z/y register kernels, their launch and their
@@ -111,31 +112,51 @@ def source_digest():
     return hs.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio of the
-    known size of a plain copy to what the same counter read for it), or
-    None when the summary is missing or the sources have changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    kv = {}
-    with open(TRAFFIC_FILE) as fh:
-        for line in fh:
-            if line.startswith("#") or not line.strip():
-                continue
-            k, _, v = line.strip().partition(" ")
-            kv[k] = v.strip()
-    if kv.get("csrc_sha256") != source_digest() or kv.get("kernel") != kernel:
-        return None
-    cb = float(kv["copy_bytes"])
-    ff = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
-    fw = cb / (float(kv["copy_write_kib"]) * 1024.0)
-    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024.0 * ff
-    write = float(kv["write_kib_per_dispatch"]) * 1024.0 * fw
-    return {"full_dispatch_bytes": round(fetch + write), "fetch_bytes": round(fetch),
-            "write_bytes": round(write), "fetch_scale": round(ff, 4), "write_scale": round(fw, 4),
-            "systems_per_dispatch": int(kv["systems_per_dispatch"]),
-            "dispatches": int(kv.get("dispatches", 0))}
+def measured_traffic(kernel, systems):
+    """HBM bytes per launch of `kernel` with `systems` systems from the
+    committed counter summaries (FETCH_SIZE and WRITE_SIZE per dispatch,
+    each scaled by the ratio of the known size of a plain copy to what the
+    same counter read for it), or None when no summary covers that kernel
+    and batch or the sources have changed since."""
+    for path in TRAFFIC_FILES:
+        if not os.path.exists(path):
+            continue
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("#") or not line.strip():
+                    continue
+                k, _, v = line.strip().partition(" ")
+                kv.setdefault(k, v.strip())
+        if (kv.get("csrc_sha256") != source_digest() or kv.get("kernel") != kernel
+                or int(kv.get("systems_per_dispatch", 0)) != systems):
+            continue
+        cb = float(kv["copy_bytes"])
+        ff = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
+        fw = cb / (float(kv["copy_write_kib"]) * 1024.0)
+        fetch = float(kv["fetch_kib_per_dispatch"]) * 1024.0 * ff
+        write = float(kv["write_kib_per_dispatch"]) * 1024.0 * fw
+        return {"file": os.path.relpath(path, ROOT), "full_dispatch_bytes": round(fetch + write),
+                "fetch_bytes": round(fetch), "write_bytes": round(write), "fetch_scale": round(ff, 4),
+                "write_scale": round(fw, 4), "systems_per_dispatch": int(kv["systems_per_dispatch"]),
+                "dispatches": int(kv.get("dispatches", 0))}
+    return None
+
+
+def attach_traffic(roofline, systems):
+    """The counter traffic of the dominant kernel, scaled to the timed
+    launches like `achieved` (counters were taken on launches with every
+    system active; system applications per launch)."""
+    tr = measured_traffic(roofline["kernel"], systems)
+    if tr is None:
+        return
+    apps, launches = roofline["system_applications"], roofline["launches"]
+    per_app = tr["full_dispatch_bytes"] / tr["systems_per_dispatch"]
+    per_launch = per_app * apps / launches
+    roofline["traffic"] = round(per_launch)
+    tr["measured_gbs"] = round(per_launch / (roofline["avg_launch_ms"] * 1e-3) / 1e9, 1)
+    tr["vs_algorithmic"] = round(per_app / roofline["bytes_per_system_application"], 4)
+    roofline["traffic_detail"] = tr
 
 
 def kernel_name(pas, N, prec):
@@ -328,18 +349,7 @@ def main():
     head, g, (xt, y, dirs, idx) = measure_gradient(w, dev, args.steps, args.warmup, bool(args.autotune))
     scale = 1.0 / B
     roofline = head["roofline"]
-    dom_kernel = roofline["kernel"]
-    tr = measured_traffic(dom_kernel) if B == 16 else None
-    if tr is not None:
-        # counters were taken on launches with every system active; scaled to
-        # the timed launches like `achieved` (system applications per launch)
-        apps, launches = roofline["system_applications"], roofline["launches"]
-        per_app = tr["full_dispatch_bytes"] / tr["systems_per_dispatch"]
-        per_launch = per_app * apps / launches
-        roofline["traffic"] = round(per_launch)
-        tr["measured_gbs"] = round(per_launch / (roofline["avg_launch_ms"] * 1e-3) / 1e9, 1)
-        tr["vs_algorithmic"] = round(per_app / roofline["bytes_per_system_application"], 4)
-        roofline["traffic_detail"] = tr
+    attach_traffic(roofline, B)
     value = head["value"]
     iters = head["solver"]["bicgstab_iters_per_step"] * args.steps
 
@@ -380,6 +390,7 @@ def main():
         cw = syn.WORKLOADS[name]
         steps = 3 if cw.N >= 256 else 5 if cw.N >= 128 else 20
         r, _, _ = measure_gradient(cw, dev, steps, 1, bool(args.autotune))
+        attach_traffic(r["roofline"], cw.B)
         r["workload"] = (f"{cw.name}: {'first-Born' if cw.model == 'born' else 'Lippmann-Schwinger'} "
                          f"mini-batch gradient, {cw.N}^3, batch {cw.B} of {cw.L}, "
                          f"{'complex64' if cw.precision == 'f32' else 'complex128'}, tol {cw.tol:g}, "
