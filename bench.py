@@ -528,10 +528,12 @@ def bench_detprop(w, dev, xt, dirs, idx, scale, steps, base_ms, d_um=1.0, cam_n=
 def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):
     """Outer iterations of Algorithm 4.1 (strategy I) on the workload's grid:
     S subsets of B illuminations (the first S B directions), x_0 = 0.5
-    x_true, step 1/20, 50 dual iterations per WPM, FP32; three variants:
+    x_true, step 1/20, 50 dual iterations per WPM, FP32; four variants:
     SR1 metrics of Algorithm 4.2 (gamma 0.8, tau_max 1e8) with cold solves,
     the same with warm-started solves, and the first-order (alpha I)
-    variant with warm-started solves.  Measurements from the library's FP32
+    variant with warm-started solves, and SR1 with tau_max below the
+    curvature scale (rank-one corrections kept, WPM metrics of rank up to
+    S).  Measurements from the library's FP32
     forward model (tol 1e-6) without noise.  The LS context takes `plan`,
     the launch shapes tuned for the gradient workload, when given."""
     import torch
@@ -555,8 +557,12 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):
     lam = 1.0 / N ** 3
     px = WProx((N, N, N), "f32")
     variants = {}
-    for name, warm, fo in (("sr1", False, False), ("sr1_warm", True, False), ("first_order_warm", True, True)):
-        qn = QNIteration(ls, px, subsets, 1.0 / 20, lam, alpha, 0.8, 1e8, prox_iters=50, warm_start=warm,
+    # sr1_clipped: tau_max = 2 alpha, below the curvature ratio <m,m>/(gamma <s,m>) of this
+    # problem, so Algorithm 4.2 keeps rank-one corrections and the WPM runs metrics of rank
+    # up to S (with tau_max = 1e8 and gamma < 1 it keeps none)
+    for name, warm, fo, tmax in (("sr1", False, False, 1e8), ("sr1_warm", True, False, 1e8),
+                                 ("first_order_warm", True, True, 1e8), ("sr1_clipped", True, False, 2 * alpha)):
+        qn = QNIteration(ls, px, subsets, 1.0 / 20, lam, alpha, 0.8, tmax, prox_iters=50, warm_start=warm,
                          first_order=fo)
         xk = x.clone()
         torch.cuda.synchronize()
@@ -568,7 +574,7 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):
             times.append(time.perf_counter() - t)
         qn.close()
         later = [t for t, inf in zip(times, infos) if inf.k > S]
-        variants[name] = {"ms_per_iter": round(float(np.mean(times)) * 1e3, 2),
+        variants[name] = {"tau_max": tmax, "ms_per_iter": round(float(np.mean(times)) * 1e3, 2),
                           "ms_per_iter_after_S": round(float(np.mean(later)) * 1e3, 2) if later else None,
                           "loss_first_last": [infos[0].loss, infos[-1].loss],
                           "u_kept": sum(int(i.u_kept) for i in infos),
