@@ -478,6 +478,10 @@ __device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti) {
 // needs R2 rows of P slots instead of R1 (LineXS::LS), at one more barrier
 // pair per round.  Both directions read their twiddles from the forward
 // table alone (W^{(j + R2 i) jj} = tf[jj R1 + j + R2 i]), TW = R1 R2.
+// The line stride is the odd one of the full exchange (the R1 = R2 layout
+// of 16 x 16 lines at N = 128, whose exchanges the counters show free of
+// bank conflicts); a stride of an odd multiple of 8 banks measured 13 times
+// the conflict cycles and a slower pass.
 template <int R1, int R2>
 struct LineXS {
   static constexpr int P = R2 + 1;

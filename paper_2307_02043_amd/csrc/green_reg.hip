@@ -287,18 +287,23 @@ __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
 }
 
 // z lines, inverse, both z parities summed, epilogue and FP64 partials.
-// grid (N^2 / LPW, 1, B); partials[(b * NP + blockIdx.x) * 4 + k]
-template <typename T, int N>
+// NTH threads, LPW = NTH / R2 lines per workgroup; grid (N^2 / LPW, 1, B);
+// partials[(b * NP + blockIdx.x) * 4 + k]
+template <typename T, int N, int NTH = RT>
 __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
-  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = RT / R2, LS = LineX<R1, R2>::LS, NI = R1 / R2;
+  constexpr int R1 = RegCfg<N>::R1, R2 = RegCfg<N>::R2, LPW = NTH / R2, LS = LineX<R1, R2>::LS, NI = R1 / R2;
   __shared__ C<T> lds[LPW * LS];
   __shared__ C<T> twt[LineX<R1, R2>::TW];
   __shared__ C<T> th[N];
-  __shared__ double red_scratch[(RT / 64) * 3];
+  __shared__ double red_scratch[(NTH / 64) * 3];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_twtab_n<T, R1, R2>(twt, a.twN, tid);
-  for (int i = tid; i < N; i += RT) th[i] = a.twH[i];
+  for (int e = tid; e < R1 * R2; e += NTH) {  // twiddle table of the N-point lines
+    const int ta = e / R1, tb = e - ta * R1;
+    twt[e] = a.twN[ta * tb];
+    if constexpr (R1 != R2) twt[R1 * R2 + tb * R2 + ta] = a.twN[ta * tb];
+  }
+  for (int i = tid; i < N; i += NTH) th[i] = a.twH[i];
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
   C<T> acc[R1], d[R1];
@@ -319,7 +324,7 @@ __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
   const int mode = a.zi_mode;
   zi_epilogue<T, N, R2, R1>(a, b, j, L, acc, red);
   if (mode >= ZI_AV_RHAT) {
-    block_sum<RT, 3>(red, red_scratch);
+    block_sum<NTH, 3>(red, red_scratch);
     if (tid == 0) {
       double* p = a.partial + ((size_t)b * gridDim.x + blockIdx.x) * 4;
       p[0] = red[0];
@@ -330,10 +335,18 @@ __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
   }
 }
 
+// Threads per workgroup of the parity-split z-inverse pass: 32 lines of
+// complex64 at N = 256 (72 KB of LDS, two workgroups per CU), so that one
+// wave instruction covers two 256-byte runs of a z plane instead of four
+// 128-byte pieces (90.5 -> 86.0 ms of z-inverse per 256^3 step; 1024
+// threads spill); 16 lines otherwise.
+template <typename T, int N>
+constexpr int rtz_r() { return (N == 256 && sizeof(T) == 4) ? 512 : RT; }
+
 template <typename T, int N>
 __global__ void __launch_bounds__(RT) k_yc_r(PassArgs<T> a) { yc_body<T, N>(a); }
 template <typename T, int N>
-__global__ void __launch_bounds__(RT) k_zi_r(PassArgs<T> a) { zi_body<T, N>(a); }
+__global__ void __launch_bounds__((rtz_r<T, N>())) k_zi_r(PassArgs<T> a) { zi_body<T, N, rtz_r<T, N>()>(a); }
 
 
 // ===========================================================================
@@ -531,7 +544,7 @@ int reg_num_partials(int N) {
     case 32: return N * N / (rtz<T, 32>() / PadCfg<32>::R2);
     case 64: return N * N / (rtz<T, 64>() / PadCfg<64>::R2);
     case 128: return N * N / (rtz<T, 128>() / PadCfg<128>::R2);
-    case 256: return N * N / (RT / RegCfg<256>::R2);
+    case 256: return N * N / (rtz_r<T, 256>() / RegCfg<256>::R2);
     default: return -1;
   }
 }
@@ -582,10 +595,12 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
     launch_xi_stockham<T, N>(a, st);
   }
   if (tm) { tm->stop(st); tm->start(P_ZI, st); }
-  if constexpr (PADZ)
+  if constexpr (PADZ) {
     hipLaunchKernelGGL((k_zi_p<T, N>), dim3(N * N / LPWZ, 1, a.B), dim3(NTZ), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_zi_r<T, N>), dim3(N * N / LPWZ, 1, a.B), blk, 0, st, a);
+  } else {
+    constexpr int NTI = rtz_r<T, N>(), LPWI = NTI / RegCfg<N>::R2;
+    hipLaunchKernelGGL((k_zi_r<T, N>), dim3(N * N / LPWI, 1, a.B), dim3(NTI), 0, st, a);
+  }
   if (tm) tm->stop(st);
 }
 
