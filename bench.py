@@ -61,6 +61,8 @@ ITER_VEC_UNITS = 13.0
 # TFLOP/s packed figure is not reachable by it.
 FP32_VALU_PEAK_TFLOPS = 78.6
 FP64_VALU_PEAK_TFLOPS = 78.6
+# wave64 VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4
 
 
 def yc_flops_per_line(N):
@@ -143,6 +145,22 @@ def measured_traffic(kernel, systems):
     return None
 
 
+def measured_sq(kernel, systems):
+    """SQ counters of a full dispatch of `kernel` (chip totals) from the
+    summary that covers it, or None (no such section, or the sources have
+    changed since)."""
+    name = "bq::" + kernel.replace(",", ", ") + ":"
+    for path in TRAFFIC_FILES:
+        if not os.path.exists(path) or measured_traffic(kernel, systems) is None:
+            continue
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith(name):
+                    items = line[len(name):].split(",")
+                    return {k: float(v) for k, v in (it.split() for it in items)}
+    return None
+
+
 def attach_traffic(roofline, systems):
     """The counter traffic of the dominant kernel, scaled to the timed
     launches like `achieved` (counters were taken on launches with every
@@ -157,6 +175,16 @@ def attach_traffic(roofline, systems):
     tr["measured_gbs"] = round(per_launch / (roofline["avg_launch_ms"] * 1e-3) / 1e9, 1)
     tr["vs_algorithmic"] = round(per_app / roofline["bytes_per_system_application"], 4)
     roofline["traffic_detail"] = tr
+    sq = measured_sq(roofline["kernel"], systems)
+    if sq and "SQ_INSTS_VALU" in sq:
+        # wave64 VALU instructions of the counted dispatch, scaled to the timed
+        # launches, against the issue rate of the SIMDs (one wave instruction
+        # per 4 cycles on each of 1024 SIMDs at 2.4 GHz)
+        per_launch_insts = sq["SQ_INSTS_VALU"] / tr["systems_per_dispatch"] * apps / launches
+        rate = per_launch_insts / (roofline["avg_launch_ms"] * 1e-3) / 1e9
+        roofline["valu_issue"] = {"instr_per_launch": round(per_launch_insts),
+                                  "achieved": round(rate, 1), "peak": VALU_ISSUE_PEAK_G,
+                                  "unit": "G wave-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK_G, 4)}
 
 
 def kernel_name(pas, N, prec):
