@@ -428,8 +428,11 @@ struct LineX {
 };
 
 // In: d[m] = x[j + R2 m].  Out: d[i R2 + k2] = X[k1 + R1 k2], k1 = j + R2 i.
+// tail = false drops the barrier after the exchange's reads, for a caller
+// that touches this LDS line no more (the kernel's last exchange); it must
+// be uniform over the workgroup.
 template <typename T, int R1, int R2, bool INV>
-__device__ inline void line_fft_t(C<T>* d, C<T>* line, int j, const C<T>* tf) {
+__device__ inline void line_fft_t(C<T>* d, C<T>* line, int j, const C<T>* tf, bool tail = true) {
   constexpr int NI = R1 / R2, P = LineX<R1, R2>::P;
   dftR<T, INV, R1>(d);
   const C<T>* w = tf + j * R1;
@@ -444,14 +447,14 @@ __device__ inline void line_fft_t(C<T>* d, C<T>* line, int j, const C<T>* tf) {
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int jj = 0; jj < R2; ++jj) d[i * R2 + jj] = rp[i * R2 * P + jj];
-  __syncthreads();
+  if (tail) __syncthreads();
 #pragma unroll
   for (int i = 0; i < NI; ++i) dftR<T, INV, R2>(&d[i * R2]);
 }
 
 // Inverse of line_fft_t (unnormalised): back to d[m] = len x[j + R2 m].
 template <typename T, int R1, int R2>
-__device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti) {
+__device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti, bool tail = true) {
   constexpr int NI = R1 / R2, P = LineX<R1, R2>::P;
   C<T>* wp = line + j * P;
 #pragma unroll
@@ -469,7 +472,7 @@ __device__ inline void line_ifft_t(C<T>* d, C<T>* line, int j, const C<T>* ti) {
   const C<T>* rp = line + j;
 #pragma unroll
   for (int k1 = 0; k1 < R1; ++k1) d[k1] = rp[k1 * P];
-  __syncthreads();
+  if (tail) __syncthreads();
   dftR<T, true, R1>(d);
 }
 
@@ -490,7 +493,7 @@ struct LineXS {
 };
 
 template <typename T, int R1, int R2, bool INV>
-__device__ inline void line_fft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf) {
+__device__ inline void line_fft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf, bool tail = true) {
   constexpr int NI = R1 / R2, P = LineXS<R1, R2>::P;
   dftR<T, INV, R1>(d);
   const C<T>* w = tf + j * R1;
@@ -508,14 +511,14 @@ __device__ inline void line_fft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf) {
     __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < R2; ++jj) d[i * R2 + jj] = rp[jj];
-    __syncthreads();
+    if (tail || i + 1 < NI) __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i) dftR<T, INV, R2>(&d[i * R2]);
 }
 
 template <typename T, int R1, int R2>
-__device__ inline void line_ifft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf) {
+__device__ inline void line_ifft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf, bool tail = true) {
   constexpr int NI = R1 / R2, P = LineXS<R1, R2>::P;
   C<T>* wp = line + j * P;
   const C<T>* rp = line + j;
@@ -532,7 +535,7 @@ __device__ inline void line_ifft_ts(C<T>* d, C<T>* line, int j, const C<T>* tf) 
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < R2; ++kk) d[i * R2 + kk] = rp[kk * P];
-    __syncthreads();
+    if (tail || i + 1 < NI) __syncthreads();
   }
   dftR<T, true, R1>(d);
 }

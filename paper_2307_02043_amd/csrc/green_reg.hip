@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(RT) k_zf_r(PassArgs<T> a) {
   for (int pz = 0; pz < 2; ++pz) {
 #pragma unroll
     for (int m = 0; m < R1; ++m) d[m] = pz ? cmul(orig[m], th[j + R2 * m]) : orig[m];
-    line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
+    line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt, pz == 0);
     C<T>* dst = a.zh + (size_t)(b * 2 + pz) * V + L;
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -278,7 +278,7 @@ __device__ __forceinline__ void yc_body(const PassArgs<T>& a) {
         const int ky = (j + R2 * i) + R1 * k2;
         d[i * R2 + k2] = cmul(d[i * R2 + k2], g[(size_t)ky * N]);
       }
-    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
+    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2, py == 0);
 #pragma unroll
     for (int m = 0; m < R1; ++m) acc[m] = acc[m] + (py ? cmulc(d[m], th[j + R2 * m]) : d[m]);
   }
@@ -316,7 +316,7 @@ __device__ __forceinline__ void zi_body(const PassArgs<T>& a) {
     for (int i = 0; i < NI; ++i)
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) d[i * R2 + k2] = sld(&src[(size_t)((j + R2 * i) + R1 * k2) * N2]);
-    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
+    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2, pz == 0);
 #pragma unroll
     for (int m = 0; m < R1; ++m) acc[m] = acc[m] + (pz ? cmulc(d[m], th[j + R2 * m]) : d[m]);
   }
@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(NTH) k_zf_p(PassArgs<T> a) {
 #pragma unroll
   for (int m = H; m < R1; ++m) d[m] = C<T>{0, 0};
   __syncthreads();  // twiddle table
-  line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt);
+  line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt, false);
   // padded frequency kp = k1 + R1 k2 (k1 = j + R2 i): class kp & 1 = j & 1,
   // plane kp >> 1; the two classes of system b are consecutive volumes
   using O = PadRaw<N, R1, R2, SZ>;
@@ -471,6 +471,16 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   // at index kp >> 1; classes (pz, 0, px) and (pz, 1, px) are 2V apart
   const brsrc rg = make_rsrc(a.ghat + (size_t)(pz * 4 + px) * V, O::g_bytes);
   const uint32_t vg = O::g_v(j, kz, kx);
+  // the transfer function is loaded before the forward transform (its
+  // latency then overlaps the transform instead of stalling the product);
+  // at R1 = 32 the 32 extra values would cost a wave per SIMD
+  C<T> g[R1];
+  if constexpr (!SPLIT) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) g[i * R2 + k2] = bload<T>(rg, vg, O::g_s(i, k2));
+  }
   __syncthreads();
   if constexpr (SPLIT)
     line_fft_ts<T, R1, R2, false>(d, &lds[line * LS], j, twt);
@@ -480,11 +490,11 @@ __global__ void __launch_bounds__(RT) k_yc_p(PassArgs<T> a) {
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
-      d[i * R2 + k2] = cmul(d[i * R2 + k2], bload<T>(rg, vg, O::g_s(i, k2)));
+      d[i * R2 + k2] = cmul(d[i * R2 + k2], SPLIT ? bload<T>(rg, vg, O::g_s(i, k2)) : g[i * R2 + k2]);
   if constexpr (SPLIT)
-    line_ifft_ts<T, R1, R2>(d, &lds[line * LS], j, twt);
+    line_ifft_ts<T, R1, R2>(d, &lds[line * LS], j, twt, false);
   else
-    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, twt);
+    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, twt, false);
 #pragma unroll
   for (int m = 0; m < H; ++m) bstore<T, true>(d[m], rc, vo, O::y_s(m));
 }
@@ -513,7 +523,7 @@ __global__ void __launch_bounds__((rtz<T, N>())) k_zi_p(PassArgs<T> a) {
     for (int k2 = 0; k2 < R2; ++k2)
       d[i * R2 + k2] = bload<T, true>(rz, vo, O::z_s(i, k2));
   __syncthreads();
-  line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2);
+  line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2, false);
   double red[3] = {0.0, 0.0, 0.0};
   const int mode = a.zi_mode;
   zi_epilogue<T, N, R2, H>(a, b, j, L, d, red);
