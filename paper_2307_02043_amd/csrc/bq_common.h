@@ -245,6 +245,66 @@ __device__ inline void dft32(C<T>* v) {
   dft32_join<T, INV, 0>(e, o, v);
 }
 
+// cos(m pi / 12), m mod 24 (exact decimal expansions: cos 15 = (sqrt 6 +
+// sqrt 2) / 4, cos 75 = (sqrt 6 - sqrt 2) / 4)
+__host__ __device__ constexpr double cos24(int m) {
+  constexpr double c[7] = {1.0,
+                           0.96592582628906828674974319972890,
+                           0.86602540378443864676372317075294,
+                           0.70710678118654752440084436210485,
+                           0.5,
+                           0.25881904510252076234889883762405,
+                           0.0};
+  const int r = ((m % 24) + 24) % 24;  // angle r pi / 12 in [0, 2 pi)
+  const int q = r <= 12 ? r : 24 - r;  // cos is even about pi
+  return q <= 6 ? c[q] : -c[12 - q];   // cos(pi - t) = -cos t
+}
+__host__ __device__ constexpr double sin24(int m) { return cos24(m + 18); }  // sin x = cos(x - pi/2)
+
+// a W24^M (its conjugate for the inverse); quarter turns are swaps
+template <typename T, bool INV, int M>
+__device__ inline C<T> tw24(C<T> a) {
+  constexpr int m = M % 24;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (m == 12) {
+    return C<T>{-a.x, -a.y};
+  } else if constexpr (m == 6) {
+    return rot90<T, INV>(a);  // W24^6 = -i
+  } else if constexpr (m == 18) {
+    return rot90<T, !INV>(a);
+  } else {
+    constexpr T wr = T(cos24(m)), wi = T(INV ? sin24(m) : -sin24(m));
+    return C<T>{a.x * wr - a.y * wi, a.x * wi + a.y * wr};
+  }
+}
+
+// 24-point DFT as 3 x 8: n = 8 n1 + n2, k = k1 + 3 k2.  DFT-3 over n1 for
+// each n2, twiddles W24^{n2 k1}, DFT-8 over n2 for each k1.
+template <typename T, bool INV, int N2>
+__device__ inline void dft24_col(const C<T>* v, C<T> (&a)[3][8]) {
+  if constexpr (N2 < 8) {
+    C<T> t[3] = {v[N2], v[8 + N2], v[16 + N2]};
+    dft3<T, INV>(t);
+    a[0][N2] = t[0];
+    a[1][N2] = tw24<T, INV, N2>(t[1]);
+    a[2][N2] = tw24<T, INV, 2 * N2>(t[2]);
+    dft24_col<T, INV, N2 + 1>(v, a);
+  }
+}
+
+template <typename T, bool INV>
+__device__ inline void dft24(C<T>* v) {
+  C<T> a[3][8];
+  dft24_col<T, INV, 0>(v, a);
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    dft8<T, INV>(a[k1]);
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) v[k1 + 3 * k2] = a[k1][k2];
+  }
+}
+
 template <typename T, bool INV, int R>
 __device__ inline void dftR(C<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v);
@@ -252,6 +312,7 @@ __device__ inline void dftR(C<T>* v) {
   else if constexpr (R == 4) dft4<T, INV>(v);
   else if constexpr (R == 8) dft8<T, INV>(v);
   else if constexpr (R == 16) dft16<T, INV>(v);
+  else if constexpr (R == 24) dft24<T, INV>(v);
   else if constexpr (R == 32) dft32<T, INV>(v);
   else static_assert(R == 2, "unsupported radix");
 }

@@ -76,6 +76,9 @@ template <typename T> bool reg_supported(int N);
 template <typename T, int N> void launch_xf_stockham(const PassArgs<T>& a, hipStream_t st);
 template <typename T, int N> void launch_xi_stockham(const PassArgs<T>& a, hipStream_t st);
 template <typename T> int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm);
+// the padded register y pass of a grid whose other passes are the LDS
+// Stockham ones (N = 96, complex64); false (nothing launched) otherwise
+template <typename T> bool pad_y_apply(const PassArgs<T>& a, hipStream_t st);
 template <typename T>
 int reg_num_partials(int N);
 // launch shapes the autotuner may choose (valid for this size and precision)

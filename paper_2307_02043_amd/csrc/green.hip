@@ -458,7 +458,7 @@ static void launch_split_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) 
   if (tm) { tm->stop(st); tm->start(P_XF, st); }
   hipLaunchKernelGGL((k_xf<T, N>), dim3(2 * N * N / TX, 1, a.B), blk, 0, st, a);
   if (tm) { tm->stop(st); tm->start(P_YC, st); }
-  hipLaunchKernelGGL((k_yc<T, N>), dim3(N / TX, N, 4 * a.B), blk, 0, st, a);
+  if (!pad_y_apply<T>(a, st)) hipLaunchKernelGGL((k_yc<T, N>), dim3(N / TX, N, 4 * a.B), blk, 0, st, a);
   if (tm) { tm->stop(st); tm->start(P_XI, st); }
   hipLaunchKernelGGL((k_xi<T, N>), dim3(2 * N * N / TX, 1, a.B), blk, 0, st, a);
   if (tm) { tm->stop(st); tm->start(P_ZI, st); }

@@ -365,15 +365,21 @@ template <int N> struct PadCfg { static constexpr bool ok = false; static conste
 BQ_PC(16, 8, 4)
 BQ_PC(32, 8, 8)
 BQ_PC(64, 16, 8)
+BQ_PC(96, 24, 8)
 BQ_PC(128, 16, 16)
 BQ_PC(256, 32, 16)
 #undef BQ_PC
+constexpr bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // The padded form is used up to N = 128, and for the y pass at N = 256 in
 // complex64 (a 512-point line takes 70 KB of LDS per 16 lines; complex128
-// would need 139 KB, so it keeps the parity-split form).
+// would need 139 KB, so it keeps the parity-split form).  At N = 96 (192-
+// point lines of 24 x 8) only the y pass is padded, in complex64: the other
+// passes of that grid are the LDS Stockham ones, which share its layouts,
+// and complex128 keeps the LDS y pass (24 values per thread in FP64 would
+// cost half the waves).
 template <typename T, int N>
 struct PadSel {
-  static constexpr bool ok = PadCfg<N>::ok && (N <= 128 || sizeof(T) == 4);
+  static constexpr bool ok = PadCfg<N>::ok && (pow2(N) ? (N <= 128 || sizeof(T) == 4) : sizeof(T) == 4);
 };
 
 
@@ -614,6 +620,22 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
   if (tm) tm->stop(st);
 }
 
+// The padded register y pass of a grid whose other passes are the LDS
+// Stockham ones (N = 96 in complex64); false if the grid has none.
+template <typename T>
+bool pad_y_apply(const PassArgs<T>& a, hipStream_t st) {
+  if constexpr (PadSel<T, 96>::ok) {
+    if (a.N == 96) {
+      constexpr int LPWY = RT / PadCfg<96>::R2;
+      hipLaunchKernelGGL((k_yc_p<T, 96>), dim3(4 * (96 * 96 / LPWY) * a.B), dim3(RT), 0, st, a);
+      return true;
+    }
+  }
+  return false;
+}
+template bool pad_y_apply<float>(const PassArgs<float>&, hipStream_t);
+template bool pad_y_apply<double>(const PassArgs<double>&, hipStream_t);
+
 template <typename T>
 int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
   const bool fused = a.xy_fused && xy_fused_supported<T>(a.N);
@@ -737,7 +759,7 @@ void audit_y(Audit& A) {
 
 template <typename T, int N>
 void audit_N(Audit& A) {
-  if constexpr (PadSel<T, N>::ok && N <= 128) {
+  if constexpr (PadSel<T, N>::ok && N <= 128 && pow2(N)) {
     audit_z<T, N, rtz<T, N>()>(A, "z lines");
     if constexpr (zf_wide_ok<T, N>()) {
       audit_z<T, N, 1024>(A, "z lines (1024-wide forward)");
@@ -752,6 +774,7 @@ void audit_T(Audit& A) {
   audit_N<T, 16>(A);
   audit_N<T, 32>(A);
   audit_N<T, 64>(A);
+  audit_N<T, 96>(A);
   audit_N<T, 128>(A);
   audit_N<T, 256>(A);
 }
