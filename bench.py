@@ -189,9 +189,10 @@ def attach_traffic(roofline, systems):
 
 def kernel_name(pas, N, prec):
     """The kernel that runs pass `pas` of G at grid N in precision prec
-    (register kernels of padded lines up to 128 and for the complex64 y pass
-    at 96 and 256, parity-split lines for the other 256 passes, LDS Stockham
-    kernels for the other grids and passes)."""
+    (register kernels of padded lines up to 128, for the complex64 z and y
+    passes at 96 and the complex64 y pass at 256, parity-split lines for
+    the other 256 passes, LDS Stockham kernels for the other grids and
+    passes)."""
     T = "float" if prec == "f32" else "double"
     if pas in ("xf", "xi", "xy"):
         return f"k_{pas}<{T},{N}>"
@@ -199,7 +200,7 @@ def kernel_name(pas, N, prec):
         suf = "_p"
     elif N == 256:
         suf = "_p" if (pas == "yc" and prec == "f32") else "_r"
-    elif N == 96 and pas == "yc" and prec == "f32":
+    elif N == 96 and prec == "f32":
         suf = "_p"
     else:
         suf = ""

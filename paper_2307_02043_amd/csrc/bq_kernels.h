@@ -76,9 +76,13 @@ template <typename T> bool reg_supported(int N);
 template <typename T, int N> void launch_xf_stockham(const PassArgs<T>& a, hipStream_t st);
 template <typename T, int N> void launch_xi_stockham(const PassArgs<T>& a, hipStream_t st);
 template <typename T> int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm);
-// the padded register y pass of a grid whose other passes are the LDS
-// Stockham ones (N = 96, complex64); false (nothing launched) otherwise
+// the padded register z and y passes of a grid whose x passes are the LDS
+// Stockham ones (N = 96, complex64); false (nothing launched) otherwise;
+// pad_num_partials: the z-inverse partials per system then, else -1
+template <typename T> bool pad_zf_apply(const PassArgs<T>& a, hipStream_t st);
 template <typename T> bool pad_y_apply(const PassArgs<T>& a, hipStream_t st);
+template <typename T> bool pad_zi_apply(const PassArgs<T>& a, hipStream_t st);
+template <typename T> int pad_num_partials(int N);
 template <typename T>
 int reg_num_partials(int N);
 // launch shapes the autotuner may choose (valid for this size and precision)

@@ -454,7 +454,7 @@ static void launch_split_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) 
   constexpr int TX = tile_w<T>(N);
   const dim3 blk(NT);
   if (tm) tm->start(P_ZF, st);
-  hipLaunchKernelGGL((k_zf<T, N>), dim3(N / TX, N, a.B), blk, 0, st, a);
+  if (!pad_zf_apply<T>(a, st)) hipLaunchKernelGGL((k_zf<T, N>), dim3(N / TX, N, a.B), blk, 0, st, a);
   if (tm) { tm->stop(st); tm->start(P_XF, st); }
   hipLaunchKernelGGL((k_xf<T, N>), dim3(2 * N * N / TX, 1, a.B), blk, 0, st, a);
   if (tm) { tm->stop(st); tm->start(P_YC, st); }
@@ -462,13 +462,14 @@ static void launch_split_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) 
   if (tm) { tm->stop(st); tm->start(P_XI, st); }
   hipLaunchKernelGGL((k_xi<T, N>), dim3(2 * N * N / TX, 1, a.B), blk, 0, st, a);
   if (tm) { tm->stop(st); tm->start(P_ZI, st); }
-  hipLaunchKernelGGL((k_zi<T, N>), dim3(N / TX, N, a.B), blk, 0, st, a);
+  if (!pad_zi_apply<T>(a, st)) hipLaunchKernelGGL((k_zi<T, N>), dim3(N / TX, N, a.B), blk, 0, st, a);
   if (tm) tm->stop(st);
 }
 
 template <typename T>
 int green_num_partials(int N) {
   if (reg_supported<T>(N)) return reg_num_partials<T>(N);
+  if (pad_num_partials<T>(N) > 0) return pad_num_partials<T>(N);
   switch (N) {
 #define BQ_NP(n) case n: return (n / tile_w<T>(n)) * n;
     BQ_NP(8) BQ_NP(12) BQ_NP(16) BQ_NP(24) BQ_NP(32) BQ_NP(48) BQ_NP(64) BQ_NP(96) BQ_NP(128) BQ_NP(256)

@@ -409,18 +409,26 @@ constexpr int rtz() { return (N == 128 && sizeof(T) == 4) ? 1024 : RT; }
 // The z-forward pass writes no partial sums, so the autotuner may also run
 // it 1024 threads wide at other sizes (complex64, where the lines fit in LDS).
 template <typename T, int N>
-constexpr bool zf_wide_ok() { return sizeof(T) == 4 && N <= 128 && PadCfg<N>::ok; }
+constexpr bool zf_wide_ok() { return sizeof(T) == 4 && N <= 128 && pow2(N) && PadCfg<N>::ok; }
+
+// Padded z lines of three or more exchange rounds (R1 = 3 R2 at N = 96) go
+// through an LDS line of R2 rows per round (18 KB per workgroup instead of
+// 55 KB for the whole 24-row line).
+template <int N>
+constexpr bool zsplit() { return PadCfg<N>::R1 / PadCfg<N>::R2 > 2; }
 
 template <typename T, int N, int NTH = rtz<T, N>()>
 __global__ void __launch_bounds__(NTH) k_zf_p(PassArgs<T> a) {
   constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = NTH / R2, NI = R1 / R2;
-  constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;  // H: nonzero inputs per thread
+  constexpr bool SPLIT = zsplit<N>();
+  constexpr int LS = SPLIT ? LineXS<R1, R2>::LS : LineX<R1, R2>::LS, H = R1 / 2;  // H: nonzero inputs per thread
+  constexpr int TW = SPLIT ? LineXS<R1, R2>::TW : LineX<R1, R2>::TW;
   constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> twt[LineX<R1, R2>::TW];
+  __shared__ C<T> twt[TW];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_twtab_pad<T, N, R1, R2, NTH>(twt, a.twH, tid);
+  load_twtab_pad<T, N, R1, R2, NTH, !SPLIT>(twt, a.twH, tid);
   const size_t N2 = (size_t)N * N, V = N2 * N;
   const int L = blockIdx.x * LPW + line;
   C<T> d[R1];
@@ -428,7 +436,10 @@ __global__ void __launch_bounds__(NTH) k_zf_p(PassArgs<T> a) {
 #pragma unroll
   for (int m = H; m < R1; ++m) d[m] = C<T>{0, 0};
   __syncthreads();  // twiddle table
-  line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt, false);
+  if constexpr (SPLIT)
+    line_fft_ts<T, R1, R2, false>(d, &lds[line * LS], j, twt, false);
+  else
+    line_fft_t<T, R1, R2, false>(d, &lds[line * LS], j, twt, false);
   // padded frequency kp = k1 + R1 k2 (k1 = j + R2 i): class kp & 1 = j & 1,
   // plane kp >> 1; the two classes of system b are consecutive volumes
   using O = PadRaw<N, R1, R2, SZ>;
@@ -510,14 +521,16 @@ template <typename T, int N>
 __global__ void __launch_bounds__((rtz<T, N>())) k_zi_p(PassArgs<T> a) {
   constexpr int NTH = rtz<T, N>();
   constexpr int R1 = PadCfg<N>::R1, R2 = PadCfg<N>::R2, LPW = NTH / R2, NI = R1 / R2;
-  constexpr int LS = LineX<R1, R2>::LS, H = R1 / 2;
+  constexpr bool SPLIT = zsplit<N>();
+  constexpr int LS = SPLIT ? LineXS<R1, R2>::LS : LineX<R1, R2>::LS, H = R1 / 2;
+  constexpr int TW = SPLIT ? LineXS<R1, R2>::TW : LineX<R1, R2>::TW;
   constexpr uint32_t SZ = sizeof(C<T>);
   __shared__ C<T> lds[LPW * LS];
-  __shared__ C<T> twt[LineX<R1, R2>::TW];
+  __shared__ C<T> twt[TW];
   __shared__ double red_scratch[(NTH / 64) * 3];
   const int b = blockIdx.z, tid = threadIdx.x, line = tid % LPW, j = tid / LPW;
   if (sys_skip(a.state, a.mask, b)) return;
-  load_twtab_pad<T, N, R1, R2, NTH>(twt, a.twH, tid);
+  load_twtab_pad<T, N, R1, R2, NTH, !SPLIT>(twt, a.twH, tid);
   const int L = blockIdx.x * LPW + line;
   using O = PadRaw<N, R1, R2, SZ>;
   const brsrc rz = make_rsrc(a.zh + (size_t)b * 2 * N * N * N, O::z_bytes);
@@ -529,7 +542,10 @@ __global__ void __launch_bounds__((rtz<T, N>())) k_zi_p(PassArgs<T> a) {
     for (int k2 = 0; k2 < R2; ++k2)
       d[i * R2 + k2] = bload<T, true>(rz, vo, O::z_s(i, k2));
   __syncthreads();
-  line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2, false);
+  if constexpr (SPLIT)
+    line_ifft_ts<T, R1, R2>(d, &lds[line * LS], j, twt, false);
+  else
+    line_ifft_t<T, R1, R2>(d, &lds[line * LS], j, R1 == R2 ? twt : twt + R1 * R2, false);
   double red[3] = {0.0, 0.0, 0.0};
   const int mode = a.zi_mode;
   zi_epilogue<T, N, R2, H>(a, b, j, L, d, red);
@@ -620,8 +636,20 @@ static void launch_reg_N(const PassArgs<T>& a, hipStream_t st, PassTimer* tm, bo
   if (tm) tm->stop(st);
 }
 
-// The padded register y pass of a grid whose other passes are the LDS
-// Stockham ones (N = 96 in complex64); false if the grid has none.
+// The padded register z and y passes of a grid whose x passes are the LDS
+// Stockham ones (N = 96 in complex64); false (nothing launched) if the grid
+// has none.  The z-inverse pass then writes N^2 / LPW partials per system.
+template <typename T>
+bool pad_zf_apply(const PassArgs<T>& a, hipStream_t st) {
+  if constexpr (PadSel<T, 96>::ok) {
+    if (a.N == 96) {
+      constexpr int LPW = rtz<T, 96>() / PadCfg<96>::R2;
+      hipLaunchKernelGGL((k_zf_p<T, 96>), dim3(96 * 96 / LPW, 1, a.B), dim3(rtz<T, 96>()), 0, st, a);
+      return true;
+    }
+  }
+  return false;
+}
 template <typename T>
 bool pad_y_apply(const PassArgs<T>& a, hipStream_t st) {
   if constexpr (PadSel<T, 96>::ok) {
@@ -633,8 +661,31 @@ bool pad_y_apply(const PassArgs<T>& a, hipStream_t st) {
   }
   return false;
 }
+template <typename T>
+bool pad_zi_apply(const PassArgs<T>& a, hipStream_t st) {
+  if constexpr (PadSel<T, 96>::ok) {
+    if (a.N == 96) {
+      constexpr int LPW = rtz<T, 96>() / PadCfg<96>::R2;
+      hipLaunchKernelGGL((k_zi_p<T, 96>), dim3(96 * 96 / LPW, 1, a.B), dim3(rtz<T, 96>()), 0, st, a);
+      return true;
+    }
+  }
+  return false;
+}
+template <typename T>
+int pad_num_partials(int N) {
+  if constexpr (PadSel<T, 96>::ok)
+    if (N == 96) return 96 * 96 / (rtz<T, 96>() / PadCfg<96>::R2);
+  return -1;
+}
+template bool pad_zf_apply<float>(const PassArgs<float>&, hipStream_t);
+template bool pad_zf_apply<double>(const PassArgs<double>&, hipStream_t);
 template bool pad_y_apply<float>(const PassArgs<float>&, hipStream_t);
 template bool pad_y_apply<double>(const PassArgs<double>&, hipStream_t);
+template bool pad_zi_apply<float>(const PassArgs<float>&, hipStream_t);
+template bool pad_zi_apply<double>(const PassArgs<double>&, hipStream_t);
+template int pad_num_partials<float>(int);
+template int pad_num_partials<double>(int);
 
 template <typename T>
 int reg_apply(const PassArgs<T>& a, hipStream_t st, PassTimer* tm) {
@@ -759,7 +810,7 @@ void audit_y(Audit& A) {
 
 template <typename T, int N>
 void audit_N(Audit& A) {
-  if constexpr (PadSel<T, N>::ok && N <= 128 && pow2(N)) {
+  if constexpr (PadSel<T, N>::ok && N <= 128) {
     audit_z<T, N, rtz<T, N>()>(A, "z lines");
     if constexpr (zf_wide_ok<T, N>()) {
       audit_z<T, N, 1024>(A, "z lines (1024-wide forward)");
