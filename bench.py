@@ -207,13 +207,14 @@ def kernel_name(pas, N, prec):
     return f"k_{pas}{suf}<{T},{N}>"
 
 
-def measure_gradient(w, dev, steps, warmup, autotune=True, prec=None, ctx_kw=None, label=None):
+def measure_gradient(w, dev, steps, warmup, autotune=True, prec=None, ctx_kw=None, label=None, event_free=False):
     """Time `steps` calls of the batched mini-batch gradient of workload w
     (after `warmup` untimed calls that also time every pass of G), inputs
     resident on the device.  Measurements from the library's own forward
     model (FP32, tol 1e-6; the Born model for a Born workload) plus noise.
-    Returns the figures of the timed steps and the context's last gradient
-    (for cross-precision checks)."""
+    With event_free, the same number of steps is then timed again with no
+    events at all (`no_events`).  Returns the figures of the timed steps and
+    the context's last gradient (for cross-precision checks)."""
     import torch
 
     import synthetic as syn
@@ -288,6 +289,17 @@ def measure_gradient(w, dev, steps, warmup, autotune=True, prec=None, ctx_kw=Non
         warm_ms, breakdown_steps = pass_ms, steps
     else:
         breakdown_steps = warmup
+    no_events = None
+    if event_free:
+        # the same number of steps with no events at all: for short steps the
+        # two events around each launch of the dominant pass are a visible
+        # share of the step
+        t1 = time.perf_counter()
+        for i in range(steps):
+            ctx.grad(xe, yt, idx, scale)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t1
+        no_events = {"value": round(B * steps / el1, 4), "ms_per_step": round(el1 / steps * 1e3, 3)}
     apps = sum(sum(inf.green_apps) for inf in infos)
     iters = sum(sum(inf.iters_fwd) + sum(inf.iters_adj) for inf in infos)
     csz = 8 if prec == "f32" else 16
@@ -325,6 +337,8 @@ def measure_gradient(w, dev, steps, warmup, autotune=True, prec=None, ctx_kw=Non
         "passes_ms_per_step": {k: round(v / breakdown_steps, 3) for k, v in warm_ms.items()},
         "autotune": tune,
     }
+    if no_events:
+        res["no_events"] = no_events
     ctx.close()
     return res, g, (xt, y, dirs, idx)
 
@@ -420,7 +434,7 @@ def main():
     for name in [c for c in args.configs.split(",") if c]:
         cw = syn.WORKLOADS[name]
         steps = 3 if cw.N >= 256 else 5 if cw.N >= 128 else 20
-        r, _, _ = measure_gradient(cw, dev, steps, 1, bool(args.autotune))
+        r, _, _ = measure_gradient(cw, dev, steps, 1, bool(args.autotune), event_free=True)
         attach_traffic(r["roofline"], cw.B)
         r["workload"] = (f"{cw.name}: {'first-Born' if cw.model == 'born' else 'Lippmann-Schwinger'} "
                          f"mini-batch gradient, {cw.N}^3, batch {cw.B} of {cw.L}, "
