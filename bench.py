@@ -93,7 +93,8 @@ def copy_calibration(dev, mib):
 
 
 TRAFFIC_FILES = (os.path.join(ROOT, "profiles", "ls_grad_128cubed_b16_f32_hbm_traffic.txt"),
-                 os.path.join(ROOT, "profiles", "ls_grad_256cubed_b32_f32_hbm_traffic.txt"))
+                 os.path.join(ROOT, "profiles", "ls_grad_256cubed_b32_f32_hbm_traffic.txt"),
+                 os.path.join(ROOT, "profiles", "ls_grad_96cubed_b8_f32_hbm_traffic.txt"))
 
 
 # sources that define the z/y register kernels, their launch and their
