@@ -2,7 +2,7 @@
 tests that the oracle cannot finish inside a test (hours of FP64 CPU work
 otherwise repeated on every run).  Calls only oracle/ and synthetic/.
 
-    python tests/golden/make_fullsize_refs.py [grad|strong|prox|all] [workers]
+    python tests/golden/make_fullsize_refs.py [grad|fields|strong|strong_fields|prox|all] [workers]
 
 grad: the 256^3 workload with contrast x1.5 (c5_ls256_f32), the first two
       illuminations of its mini-batch.  Measurements y = H(x_true) (oracle
@@ -16,6 +16,15 @@ strong: the strongly scattering 128^3 workload (c6_ls128_strong), its first
       30 dB noise, stored as complex128, and the FP64 gradient and loss at
       x_true with scale 1/2 (tol 1e-13 on both sides of the comparison),
       kept at 8192 seeded voxels, with the iteration counts.
+fields: the 256^3 workload's whole launch set of 32 illuminations with
+      stand-in detector images (synthetic.detector_images, stored as
+      complex64) at x = 0.5 x_true (in float32 values): the forward and the
+      adjoint fields of the first and the last system (oracle solves at tol
+      1e-12), kept at 8192 seeded voxels with their whole-array norms.
+strong_fields: the strongly scattering workload's whole launch set of 15
+      with stand-in detector images (complex64) at its evaluation point (in
+      float32 values): forward and adjoint fields of the first and the last
+      system (tol 1e-13), kept at 8192 seeded voxels with their norms.
 prox: the weighted TV prox of the same workload: iso TV, nonnegativity,
       metric tau I + u u^T (rank one), lambda 1e-3, 200 dual iterations
       (Section 4.1 iteration, Theorem 3.1 projection), kept at 8192 seeded
@@ -89,6 +98,74 @@ def make_grad(workers: int) -> None:
              inputs=array_digest(x, dirs))
 
 
+def c5_field_inputs():
+    """x, y, directions and batch of the 256^3 launch-set field references
+    (the GPU test rebuilds them the same way)."""
+    w = syn.WORKLOADS["c5_ls256_f32"]
+    x = (0.5 * syn.scattering_potential(syn.make_phantom(w))).astype(np.float32).astype(np.float64)
+    y = syn.detector_images(w.B, w.N, np.random.default_rng(w.seed("noise") + 100)).astype(np.complex64)
+    return x, y, syn.workload_directions(w), [int(i) for i in syn.batch_indices(w)]
+
+
+def make_fields(workers: int) -> None:
+    w = syn.WORKLOADS["c5_ls256_f32"]
+    geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+    t0 = time.time()
+    m = lsmodel.LSModel(geom, workers=workers)
+    x, y, dirs, idx = c5_field_inputs()
+    sel = sample_index(x.size, 7259)
+    out = {}
+    for b in (0, w.B - 1):
+        uin = lsmodel.incident_field(geom, dirs[idx[b]])
+        u, itf, sf, _ = m.solve_forward(x, uin, 1e-12, 500)
+        r = m.detector(u - uin) - y[b].astype(np.complex128)
+        wv, ita, sa, _ = m.solve_adjoint(x, m.GH(m.detector_T(r)), 1e-12, 500)
+        assert sf == lsmodel.CONVERGED and sa == lsmodel.CONVERGED
+        print(f"system {b}: {time.time() - t0:.0f} s, iterations {itf} / {ita}", flush=True)
+        out[f"u{b}_sel"] = u.ravel()[sel]
+        out[f"w{b}_sel"] = wv.ravel()[sel]
+        out[f"u{b}_norm"] = np.linalg.norm(u)
+        out[f"w{b}_norm"] = np.linalg.norm(wv)
+        out[f"loss{b}"] = 0.5 * float(np.vdot(r, r).real)
+        out[f"iters{b}"] = np.array([itf, ita], np.int32)
+    np.savez(os.path.join(HERE, "c5_fields256_b32.npz"), sel=sel, systems=np.array([0, w.B - 1], np.int32),
+             digest=source_digest(GRAD_SOURCES), inputs=array_digest(x, y, dirs), **out)
+
+
+def c6_field_inputs():
+    """x, y, directions and batch of the strongly scattering launch-set field
+    references (the GPU test rebuilds them the same way)."""
+    w = syn.WORKLOADS["c6_ls128_strong"]
+    x = (w.x_eval_scale * syn.scattering_potential(syn.make_phantom(w))).astype(np.float32).astype(np.float64)
+    y = syn.detector_images(w.B, w.N, np.random.default_rng(w.seed("noise") + 100)).astype(np.complex64)
+    return x, y, syn.workload_directions(w), [int(i) for i in syn.batch_indices(w)]
+
+
+def make_strong_fields(workers: int) -> None:
+    w = syn.WORKLOADS["c6_ls128_strong"]
+    geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+    t0 = time.time()
+    m = lsmodel.LSModel(geom, workers=workers)
+    x, y, dirs, idx = c6_field_inputs()
+    sel = sample_index(x.size, 7260)
+    out = {}
+    for b in (0, w.B - 1):
+        uin = lsmodel.incident_field(geom, dirs[idx[b]])
+        u, itf, sf, _ = m.solve_forward(x, uin, 1e-13, 1000)
+        r = m.detector(u - uin) - y[b].astype(np.complex128)
+        wv, ita, sa, _ = m.solve_adjoint(x, m.GH(m.detector_T(r)), 1e-13, 1000)
+        assert sf == lsmodel.CONVERGED and sa == lsmodel.CONVERGED
+        print(f"system {b}: {time.time() - t0:.0f} s, iterations {itf} / {ita}", flush=True)
+        out[f"u{b}_sel"] = u.ravel()[sel]
+        out[f"w{b}_sel"] = wv.ravel()[sel]
+        out[f"u{b}_norm"] = np.linalg.norm(u)
+        out[f"w{b}_norm"] = np.linalg.norm(wv)
+        out[f"iters{b}"] = np.array([itf, ita], np.int32)
+    np.savez(os.path.join(HERE, "c6_fields128_strong_b15.npz"), sel=sel,
+             systems=np.array([0, w.B - 1], np.int32), digest=source_digest(GRAD_SOURCES),
+             inputs=array_digest(x, y, dirs), **out)
+
+
 def make_strong(workers: int) -> None:
     w = syn.WORKLOADS["c6_ls128_strong"]
     geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
@@ -127,7 +204,11 @@ if __name__ == "__main__":
     workers = int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1)
     if what in ("grad", "all"):
         make_grad(workers)
+    if what in ("fields", "all"):
+        make_fields(workers)
     if what in ("strong", "all"):
         make_strong(workers)
+    if what in ("strong_fields", "all"):
+        make_strong_fields(workers)
     if what in ("prox", "all"):
         make_prox()

@@ -7,6 +7,14 @@ bench.py runs.
   1e-6, oracle tol 1e-13).
 * 128^3, complex128, 4 illuminations: gradient and loss against the
   oracle's (1e-10; both sides tol 1e-13), the complex128 y pass at 128.
+* 96^3, complex64, the 96^3 workload's launch set of 8: forward and adjoint
+  fields of its first and last systems, element by element (live oracle).
+* 256^3, complex64, the benchmark's launch set of 32: forward and adjoint
+  fields of the first and the last system against oracle solves stored at
+  8192 seeded voxels, with their norms (2e-4).
+* the strongly scattering 128^3 workload's launch set of 15, FP32 and FP64:
+  forward and adjoint fields of its first and last systems against stored
+  oracle solves (tol 1e-13) at 8192 voxels.
 * 256^3, complex64, 2 illuminations of the 256^3 workload: gradient and loss
   against the oracle's, stored by tests/golden/make_fullsize_refs.py at 8192
   seeded voxels (the relative error over the sample estimates the
@@ -158,6 +166,42 @@ def test_128_f64_gradient_matches_oracle(dev):
 
 
 # --------------------------------------------------------------------------
+# 96^3 (radix 3)
+# --------------------------------------------------------------------------
+C3 = syn.WORKLOADS["c3_ls96_f32"]
+
+
+def test_96_launch_set_of_8_fields_match_oracle(dev):
+    """The 96^3 workload's whole launch set of 8 (the benchmark's), FP32 at
+    tol 1e-6 (padded 24 x 8 register z and y passes, LDS x passes): forward
+    and adjoint fields of the first and the last system element by element
+    against oracle solves at tol 1e-13; stand-in detector images."""
+    N, B = C3.N, C3.B
+    x = (0.5 * syn.scattering_potential(syn.make_phantom(C3))).astype(np.float32).astype(np.float64)
+    y = syn.detector_images(B, N, np.random.default_rng(C3.seed("noise") + 100)).astype(np.complex64)
+    dirs = syn.workload_directions(C3)
+    idx = [int(i) for i in syn.batch_indices(C3)]
+    ctx = _ctx(C3, "f32", tol=1e-6, max_iter=300)
+    u = torch.zeros((B, N, N, N), dtype=torch.complex64, device=dev)
+    w = torch.zeros_like(u)
+    g, f, info = ctx.grad_ws(torch.from_numpy(x).to(dev, torch.float32), torch.from_numpy(y).to(dev), idx,
+                             1.0 / B, u, w, start=False)
+    assert info.status == 0 and len(info.iters_fwd) == B
+    ctx.close()
+    m = lsmodel.LSModel(lsmodel.Geometry(N=N, h=C3.h_um, lambda0=C3.lambda0_um, n_b=C3.n_b), workers=WORKERS)
+    for b in (0, B - 1):
+        uin = lsmodel.incident_field(m.geom, dirs[idx[b]])
+        ur, _, sf, _ = m.solve_forward(x, uin, 1e-13, 300)
+        r = m.detector(ur - uin) - y[b].astype(np.complex128)
+        wr, _, sa, _ = m.solve_adjoint(x, m.GH(m.detector_T(r)), 1e-13, 300)
+        assert sf == lsmodel.CONVERGED and sa == lsmodel.CONVERGED
+        eu = _rel(u[b].cpu().numpy(), ur)
+        ew = _rel(np.conj(w[b].cpu().numpy()), wr)
+        assert eu < 2e-4 and ew < 2e-4, (b, eu, ew)
+        print(f"96^3 launch set of 8, FP32, system {b}: field {eu:.2e}, adjoint field {ew:.2e}")
+
+
+# --------------------------------------------------------------------------
 # 256^3 (stored oracle results)
 # --------------------------------------------------------------------------
 C5 = syn.WORKLOADS["c5_ls256_f32"]
@@ -181,6 +225,40 @@ def test_256_f32_gradient_matches_stored_oracle(dev):
     print(f"256^3 FP32 gradient of 2 (8192 voxels): {err:.2e}, loss {abs(f - float(ref['loss'])) / float(ref['loss']):.2e}")
     assert abs(float(torch.linalg.norm(g.double())) - float(ref["g_norm"])) < 2e-4 * float(ref["g_norm"])
     assert abs(f - float(ref["loss"])) < 2e-4 * float(ref["loss"])
+
+
+def test_256_launch_set_of_32_fields_match_stored_oracle(dev):
+    """The 256^3 workload's whole launch set of 32 (the benchmark's), FP32 at
+    tol 1e-6: the forward and adjoint fields of the first and the last
+    system against the oracle's (tol 1e-12), stored at 8192 voxels with the
+    whole-array norms; stand-in detector images as at 128^3."""
+    N, B = C5.N, C5.B
+    x = (0.5 * syn.scattering_potential(syn.make_phantom(C5))).astype(np.float32).astype(np.float64)
+    y = syn.detector_images(B, N, np.random.default_rng(C5.seed("noise") + 100)).astype(np.complex64)
+    dirs = syn.workload_directions(C5)
+    ref = _golden("c5_fields256_b32.npz", ("oracle/green.py", "oracle/lsmodel.py"), x, y, dirs)
+    idx = [int(i) for i in syn.batch_indices(C5)]
+    ctx = _ctx(C5, "f32", tol=1e-6, max_iter=500)
+    u = torch.zeros((B, N, N, N), dtype=torch.complex64, device=dev)
+    w = torch.zeros_like(u)
+    g, f, info = ctx.grad_ws(torch.from_numpy(x).to(dev, torch.float32), torch.from_numpy(y).to(dev), idx,
+                             1.0 / B, u, w, start=False)
+    assert info.status == 0 and len(info.iters_fwd) == B
+    ctx.close()
+    sel = torch.from_numpy(ref["sel"]).to(dev)
+    for b in [int(t) for t in ref["systems"]]:
+        us = u[b].reshape(-1)[sel].cpu().numpy()
+        # the library keeps the conjugated adjoint field (it solves the conjugate system)
+        ws = np.conj(w[b].reshape(-1)[sel].cpu().numpy())
+        eu, ew = _rel(us, ref[f"u{b}_sel"]), _rel(ws, ref[f"w{b}_sel"])
+        assert eu < 2e-4 and ew < 2e-4, (b, eu, ew)
+        nu = float(torch.linalg.norm(u[b].to(torch.complex128)))
+        nw = float(torch.linalg.norm(w[b].to(torch.complex128)))
+        assert abs(nu - float(ref[f"u{b}_norm"])) < 2e-4 * float(ref[f"u{b}_norm"])
+        assert abs(nw - float(ref[f"w{b}_norm"])) < 2e-4 * float(ref[f"w{b}_norm"])
+        print(f"256^3 launch set of 32, FP32, system {b}: field {eu:.2e}, adjoint field {ew:.2e} "
+              f"(8192 voxels); iterations {info.iters_fwd[b]} / {info.iters_adj[b]} against "
+              f"{ref[f'iters{b}'].tolist()} at the oracle's tol 1e-12")
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -237,3 +315,40 @@ def test_128_strong_scattering_f64_gradient_matches_stored_oracle(dev):
               f"{info.iters_fwd} / {info.iters_adj} against {ref['iters'].tolist()}")
         assert abs(float(torch.linalg.norm(g.double())) - float(ref["g_norm"])) < lim * float(ref["g_norm"])
         assert abs(f - float(ref["loss"])) < lim * float(ref["loss"])
+
+
+def test_128_strong_launch_set_of_15_fields_match_stored_oracle(dev):
+    """The strongly scattering workload's whole launch set of 15 (the
+    benchmark's, with per-system iteration counts that differ): forward and
+    adjoint fields of the first and the last system against the oracle's
+    (tol 1e-13), stored at 8192 voxels with their norms; FP32 at tol 1e-6
+    (2e-4) and FP64 at tol 1e-13 (1e-10); stand-in detector images."""
+    N, B = C6.N, C6.B
+    x = (C6.x_eval_scale * syn.scattering_potential(syn.make_phantom(C6))).astype(np.float32).astype(np.float64)
+    y = syn.detector_images(B, N, np.random.default_rng(C6.seed("noise") + 100)).astype(np.complex64)
+    dirs = syn.workload_directions(C6)
+    ref = _golden("c6_fields128_strong_b15.npz", ("oracle/green.py", "oracle/lsmodel.py"), x, y, dirs)
+    idx = [int(i) for i in syn.batch_indices(C6)]
+    sel = torch.from_numpy(ref["sel"]).to(dev)
+    for prec, tol, lim in (("f32", 1e-6, 2e-4), ("f64", 1e-13, 1e-10)):
+        rd, cd = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+        ctx = _ctx(C6, prec, tol=tol, max_iter=1000)
+        u = torch.zeros((B, N, N, N), dtype=cd, device=dev)
+        w = torch.zeros_like(u)
+        g, f, info = ctx.grad_ws(torch.from_numpy(x).to(dev, rd), torch.from_numpy(y).to(dev, cd), idx,
+                                 1.0 / B, u, w, start=False)
+        assert info.status == 0 and len(info.iters_fwd) == B
+        ctx.close()
+        for b in [int(t) for t in ref["systems"]]:
+            us = u[b].reshape(-1)[sel].cpu().numpy()
+            ws = np.conj(w[b].reshape(-1)[sel].cpu().numpy())
+            eu, ew = _rel(us, ref[f"u{b}_sel"]), _rel(ws, ref[f"w{b}_sel"])
+            print(f"strongly scattering 128^3 launch set of 15, {prec}, system {b}: field {eu:.2e}, "
+                  f"adjoint field {ew:.2e} (8192 voxels); iterations {info.iters_fwd[b]} / "
+                  f"{info.iters_adj[b]} against {ref[f'iters{b}'].tolist()}")
+            assert eu < lim and ew < lim, (prec, b, eu, ew)
+            nu = float(torch.linalg.norm(u[b].to(torch.complex128)))
+            nw = float(torch.linalg.norm(w[b].to(torch.complex128)))
+            assert abs(nu - float(ref[f"u{b}_norm"])) < lim * float(ref[f"u{b}_norm"])
+            assert abs(nw - float(ref[f"w{b}_norm"])) < lim * float(ref[f"w{b}_norm"])
+        del u, w
