@@ -356,7 +356,8 @@ def main():
                     help="BiCGSTAB iterations of the oracle sample with all cores (0: skip)")
     ap.add_argument("--cpu-iters-1t", type=int, default=2,
                     help="BiCGSTAB iterations of the single-thread oracle sample (0: skip)")
-    ap.add_argument("--configs", default="c1_ls32_f64,c2_born64_f32,c3_ls96_f32,c5_ls256_f32,c6_ls128_strong",
+    ap.add_argument("--configs", default="c1_ls32_f64,c2_born64_f32,c3_ls96_f32,c5_ls256_f32,c6_ls128_strong,"
+                                         "c7_ls256_strong",
                     help="other workloads whose gradient is timed alongside ('' to skip)")
     ap.add_argument("--prox-workload", default="c5_ls256_f32",
                     help="workload whose weighted prox is timed alongside ('' to skip)")

@@ -89,6 +89,13 @@ WORKLOADS = {
                                 model="ls", precision="f32", tol=1e-5,
                                 max_iter=300, phantom="cell_solid",
                                 max_polar_deg=42.0, x_eval_scale=1.0),
+    # the 256^3 configuration in its strong multiple-scattering regime: a
+    # solid cell body of delta n 0.037 with nucleoli of 0.06 (the largest
+    # contrast that configuration names), gradient at the phantom itself
+    "c7_ls256_strong": Workload("c7_ls256_strong", 7, N=256, L=120, B=32,
+                                model="ls", precision="f32", tol=1e-5,
+                                max_iter=300, phantom="cell_solid",
+                                contrast_scale=0.06 / 0.097, x_eval_scale=1.0),
 }
 
 

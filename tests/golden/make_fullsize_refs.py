@@ -2,7 +2,7 @@
 tests that the oracle cannot finish inside a test (hours of FP64 CPU work
 otherwise repeated on every run).  Calls only oracle/ and synthetic/.
 
-    python tests/golden/make_fullsize_refs.py [grad|fields|strong|strong_fields|prox|all] [workers]
+    python tests/golden/make_fullsize_refs.py [grad|fields|strong|strong_fields|strong256_fields|prox|all] [workers]
 
 grad: the 256^3 workload with contrast x1.5 (c5_ls256_f32), the first two
       illuminations of its mini-batch.  Measurements y = H(x_true) (oracle
@@ -25,6 +25,8 @@ strong_fields: the strongly scattering workload's whole launch set of 15
       with stand-in detector images (complex64) at its evaluation point (in
       float32 values): forward and adjoint fields of the first and the last
       system (tol 1e-13), kept at 8192 seeded voxels with their norms.
+strong256_fields: the strongly scattering 256^3 workload (c7_ls256_strong)
+      in the same way, oracle tol 1e-11.
 prox: the weighted TV prox of the same workload: iso TV, nonnegativity,
       metric tau I + u u^T (rank one), lambda 1e-3, 200 dual iterations
       (Section 4.1 iteration, Theorem 3.1 projection), kept at 8192 seeded
@@ -166,6 +168,41 @@ def make_strong_fields(workers: int) -> None:
              inputs=array_digest(x, y, dirs), **out)
 
 
+def c7_field_inputs():
+    """x, y, directions and batch of the strongly scattering 256^3
+    launch-set field references (the GPU test rebuilds them the same way)."""
+    w = syn.WORKLOADS["c7_ls256_strong"]
+    x = (w.x_eval_scale * syn.scattering_potential(syn.make_phantom(w))).astype(np.float32).astype(np.float64)
+    y = syn.detector_images(w.B, w.N, np.random.default_rng(w.seed("noise") + 100)).astype(np.complex64)
+    return x, y, syn.workload_directions(w), [int(i) for i in syn.batch_indices(w)]
+
+
+def make_strong256_fields(workers: int) -> None:
+    w = syn.WORKLOADS["c7_ls256_strong"]
+    geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+    t0 = time.time()
+    m = lsmodel.LSModel(geom, workers=workers)
+    x, y, dirs, idx = c7_field_inputs()
+    sel = sample_index(x.size, 7261)
+    out = {}
+    for b in (0, w.B - 1):
+        uin = lsmodel.incident_field(geom, dirs[idx[b]])
+        u, itf, sf, _ = m.solve_forward(x, uin, 1e-11, 1000)
+        print(f"system {b} forward: {time.time() - t0:.0f} s, iterations {itf}", flush=True)
+        r = m.detector(u - uin) - y[b].astype(np.complex128)
+        wv, ita, sa, _ = m.solve_adjoint(x, m.GH(m.detector_T(r)), 1e-11, 1000)
+        assert sf == lsmodel.CONVERGED and sa == lsmodel.CONVERGED
+        print(f"system {b}: {time.time() - t0:.0f} s, iterations {itf} / {ita}", flush=True)
+        out[f"u{b}_sel"] = u.ravel()[sel]
+        out[f"w{b}_sel"] = wv.ravel()[sel]
+        out[f"u{b}_norm"] = np.linalg.norm(u)
+        out[f"w{b}_norm"] = np.linalg.norm(wv)
+        out[f"iters{b}"] = np.array([itf, ita], np.int32)
+    np.savez(os.path.join(HERE, "c7_fields256_strong_b32.npz"), sel=sel,
+             systems=np.array([0, w.B - 1], np.int32), digest=source_digest(GRAD_SOURCES),
+             inputs=array_digest(x, y, dirs), **out)
+
+
 def make_strong(workers: int) -> None:
     w = syn.WORKLOADS["c6_ls128_strong"]
     geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
@@ -210,5 +247,7 @@ if __name__ == "__main__":
         make_strong(workers)
     if what in ("strong_fields", "all"):
         make_strong_fields(workers)
+    if what in ("strong256_fields", "all"):
+        make_strong256_fields(workers)
     if what in ("prox", "all"):
         make_prox()

@@ -15,6 +15,8 @@ bench.py runs.
 * the strongly scattering 128^3 workload's launch set of 15, FP32 and FP64:
   forward and adjoint fields of its first and last systems against stored
   oracle solves (tol 1e-13) at 8192 voxels.
+* the strongly scattering 256^3 workload's launch set of 32, FP32: the same
+  against stored oracle solves (tol 1e-11).
 * 256^3, complex64, 2 illuminations of the 256^3 workload: gradient and loss
   against the oracle's, stored by tests/golden/make_fullsize_refs.py at 8192
   seeded voxels (the relative error over the sample estimates the
@@ -352,3 +354,41 @@ def test_128_strong_launch_set_of_15_fields_match_stored_oracle(dev):
             assert abs(nu - float(ref[f"u{b}_norm"])) < lim * float(ref[f"u{b}_norm"])
             assert abs(nw - float(ref[f"w{b}_norm"])) < lim * float(ref[f"w{b}_norm"])
         del u, w
+
+
+C7 = syn.WORKLOADS["c7_ls256_strong"]
+
+
+def test_256_strong_launch_set_of_32_fields_match_stored_oracle(dev):
+    """The 256^3 configuration in its strong multiple-scattering regime
+    (solid body, nucleoli of delta n 0.06; 24-28 iterations per solve at tol
+    1e-5, differing per system), its whole launch set of 32, FP32 at tol
+    1e-6: forward and adjoint fields of the first and the last system
+    against the oracle's (tol 1e-11), stored at 8192 voxels with their
+    norms; stand-in detector images."""
+    N, B = C7.N, C7.B
+    x = (C7.x_eval_scale * syn.scattering_potential(syn.make_phantom(C7))).astype(np.float32).astype(np.float64)
+    y = syn.detector_images(B, N, np.random.default_rng(C7.seed("noise") + 100)).astype(np.complex64)
+    dirs = syn.workload_directions(C7)
+    ref = _golden("c7_fields256_strong_b32.npz", ("oracle/green.py", "oracle/lsmodel.py"), x, y, dirs)
+    idx = [int(i) for i in syn.batch_indices(C7)]
+    ctx = _ctx(C7, "f32", tol=1e-6, max_iter=1000)
+    u = torch.zeros((B, N, N, N), dtype=torch.complex64, device=dev)
+    w = torch.zeros_like(u)
+    g, f, info = ctx.grad_ws(torch.from_numpy(x).to(dev, torch.float32), torch.from_numpy(y).to(dev), idx,
+                             1.0 / B, u, w, start=False)
+    assert info.status == 0 and len(info.iters_fwd) == B
+    ctx.close()
+    sel = torch.from_numpy(ref["sel"]).to(dev)
+    for b in [int(t) for t in ref["systems"]]:
+        us = u[b].reshape(-1)[sel].cpu().numpy()
+        ws = np.conj(w[b].reshape(-1)[sel].cpu().numpy())
+        eu, ew = _rel(us, ref[f"u{b}_sel"]), _rel(ws, ref[f"w{b}_sel"])
+        print(f"strongly scattering 256^3 launch set of 32, FP32, system {b}: field {eu:.2e}, adjoint field "
+              f"{ew:.2e} (8192 voxels); iterations {info.iters_fwd[b]} / {info.iters_adj[b]} against "
+              f"{ref[f'iters{b}'].tolist()} at the oracle's tol 1e-11")
+        assert eu < 2e-4 and ew < 2e-4, (b, eu, ew)
+        nu = float(torch.linalg.norm(u[b].to(torch.complex128)))
+        nw = float(torch.linalg.norm(w[b].to(torch.complex128)))
+        assert abs(nu - float(ref[f"u{b}_norm"])) < 2e-4 * float(ref[f"u{b}_norm"])
+        assert abs(nw - float(ref[f"w{b}_norm"])) < 2e-4 * float(ref[f"w{b}_norm"])
