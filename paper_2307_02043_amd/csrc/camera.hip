@@ -3,67 +3,78 @@
 // interpolation of the window's samples at the camera's pixel centres
 // (reading of the camera geometry; the paper's cameras have pixel counts of
 // their own, Section 6).  The adjoint takes an M x M image r to D^H r conj(D).
-// Both are two batched complex matrix products, run by one tiled kernel.
+// Both are two batched complex matrix products, run on the matrix cores.
 #include "bq_kernels.h"
 
 namespace bq {
 
 // C_b(i, j) = sum_k opA(A_b(i, k)) opB(B_b(k, j)) for b < grid z, with
 // element (i, k) of A_b at A + b sAb + i sAi + k sAk (sAb = 0: one matrix
-// for all b), opA = conj when conjA; the same for B and C.  16 x 16 output
-// tiles per 256-thread workgroup, K in chunks of 16 through LDS; the
-// accumulation runs in the element type.
+// for all b), opA = conj when conjA; the same for B and C.
+//
+// Matrix cores: each wave owns a 16 x 16 output tile and steps through K
+// four at a time with the 16 x 16 x 4 MFMA of the element type (FP32 or
+// FP64 products, accumulation in the element type); a complex product is
+// four real ones, Re += Ar Br - Ai Bi and Im += Ar Bi + Ai Br.  Lane l
+// supplies A(i0 + l mod 16, k0 + l / 16) and B(k0 + l / 16, j0 + l mod 16);
+// output r of lane l is C(i0 + 4 (l / 16) + r, j0 + l mod 16) for FP32 and
+// C(i0 + l / 16 + 4 r, j0 + l mod 16) for FP64.  Operands past the matrix
+// edges are zeros, so every lane of a wave issues every MFMA.  Four waves
+// per workgroup take a 32 x 32 block of C.
 struct GemmDesc {
   int I, J, K;
   long long sAb, sAi, sAk, sBb, sBk, sBj, sCb, sCi, sCj;
   int conjA, conjB;
 };
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  using V = mfma_f4;
+  static __device__ inline V mac(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <> struct Mfma<double> {
+  using V = mfma_d4;
+  static __device__ inline V mac(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_cgemm(const C<T>* A, const C<T>* Bm, C<T>* Cm, GemmDesc d) {
-  __shared__ C<T> As[16][17];
-  __shared__ C<T> Bs[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  using M = Mfma<T>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = (blockIdx.y * 2 + (wave >> 1)) * 16, j0 = (blockIdx.x * 2 + (wave & 1)) * 16;
   const long long b = blockIdx.z;
   const C<T>* Ab = A + b * d.sAb;
   const C<T>* Bb = Bm + b * d.sBb;
-  C<T> acc{0, 0};
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
-    // A tile rows i0..i0+15, columns k0..k0+15; B tile rows k0.., columns j0..
-    {
-      const int ai = blockIdx.y * 16 + ty, ak = k0 + tx;
-      C<T> v{0, 0};
-      if (ai < d.I && ak < d.K) {
-        v = Ab[ai * d.sAi + ak * d.sAk];
-        if (d.conjA) v.y = -v.y;
-      }
-      As[ty][tx] = v;
-      const int bk = k0 + ty, bj = blockIdx.x * 16 + tx;
-      C<T> w{0, 0};
-      if (bk < d.K && bj < d.J) {
-        w = Bb[bk * d.sBk + bj * d.sBj];
-        if (d.conjB) w.y = -w.y;
-      }
-      Bs[ty][tx] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const C<T> a = As[ty][kk], bb = Bs[kk][tx];
-      acc.x = fma(a.x, bb.x, acc.x);
-      acc.x = fma(-a.y, bb.y, acc.x);
-      acc.y = fma(a.x, bb.y, acc.y);
-      acc.y = fma(a.y, bb.x, acc.y);
-    }
-    __syncthreads();
+  const int ia = i0 + (lane & 15), jb = j0 + (lane & 15), kl = lane >> 4;
+  typename M::V re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < d.K; k0 += 4) {
+    const int k = k0 + kl;
+    C<T> a{0, 0}, w{0, 0};
+    if (ia < d.I && k < d.K) a = Ab[ia * d.sAi + k * d.sAk];
+    if (k < d.K && jb < d.J) w = Bb[k * d.sBk + jb * d.sBj];
+    if (d.conjA) a.y = -a.y;
+    if (d.conjB) w.y = -w.y;
+    re = M::mac(a.x, w.x, re);
+    re = M::mac(-a.y, w.y, re);
+    im = M::mac(a.x, w.y, im);
+    im = M::mac(a.y, w.x, im);
   }
-  if (i < d.I && j < d.J) Cm[b * d.sCb + i * d.sCi + j * d.sCj] = acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + M::row(lane, r), j = jb;
+    if (i < d.I && j < d.J) Cm[b * d.sCb + i * d.sCi + j * d.sCj] = C<T>{re[r], im[r]};
+  }
 }
 
 template <typename T>
 static void cgemm(int B, const C<T>* A, const C<T>* Bm, C<T>* Cm, const GemmDesc& d, hipStream_t st) {
-  const dim3 grid((d.J + 15) / 16, (d.I + 15) / 16, B);
+  const dim3 grid((d.J + 31) / 32, (d.I + 31) / 32, B);
   hipLaunchKernelGGL((k_cgemm<T>), grid, dim3(256), 0, st, A, Bm, Cm, d);
 }
 
