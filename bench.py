@@ -157,8 +157,10 @@ def measured_sq(kernel, systems):
         with open(path) as fh:
             for line in fh:
                 if line.startswith(name):
-                    items = line[len(name):].split(",")
-                    return {k: float(v) for k, v in (it.split() for it in items)}
+                    try:
+                        return {k: float(v) for k, v in (it.split() for it in line[len(name):].split(","))}
+                    except ValueError:  # not a counter line of the expected form
+                        return None
     return None
 
 
