@@ -132,13 +132,16 @@ def measured_traffic(kernel, systems):
                 k, _, v = line.strip().partition(" ")
                 kv.setdefault(k, v.strip())
         if (kv.get("csrc_sha256") != source_digest() or kv.get("kernel") != kernel
-                or int(kv.get("systems_per_dispatch", 0)) != systems):
+                or kv.get("systems_per_dispatch") != str(systems)):
             continue
-        cb = float(kv["copy_bytes"])
-        ff = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
-        fw = cb / (float(kv["copy_write_kib"]) * 1024.0)
-        fetch = float(kv["fetch_kib_per_dispatch"]) * 1024.0 * ff
-        write = float(kv["write_kib_per_dispatch"]) * 1024.0 * fw
+        try:
+            cb = float(kv["copy_bytes"])
+            ff = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
+            fw = cb / (float(kv["copy_write_kib"]) * 1024.0)
+            fetch = float(kv["fetch_kib_per_dispatch"]) * 1024.0 * ff
+            write = float(kv["write_kib_per_dispatch"]) * 1024.0 * fw
+        except (KeyError, ValueError, ZeroDivisionError):  # an incomplete summary reports no traffic
+            return None
         return {"file": os.path.relpath(path, ROOT), "full_dispatch_bytes": round(fetch + write),
                 "fetch_bytes": round(fetch), "write_bytes": round(write), "fetch_scale": round(ff, 4),
                 "write_scale": round(fw, 4), "systems_per_dispatch": int(kv["systems_per_dispatch"]),
