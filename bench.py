@@ -625,12 +625,22 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
         qn.close()
+        # the gradient alone at the last iterate (cold solves, first subset):
+        # what the outer iteration's gradient costs there, against the
+        # benchmark's gradient at 0.5 x_true
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, ginfo = ls.grad(xk, y[subsets[0]], subsets[0], S / w.L)
+        torch.cuda.synchronize()
+        grad_at_iterate_ms = (time.perf_counter() - t) * 1e3
         later = [t for t, inf in zip(times, infos) if inf.k > S]
         variants[name] = {"tau_max": tmax, "ms_per_iter": round(float(np.mean(times)) * 1e3, 2),
                           "ms_per_iter_after_S": round(float(np.mean(later)) * 1e3, 2) if later else None,
                           "loss_first_last": [infos[0].loss, infos[-1].loss],
                           "u_kept": sum(int(i.u_kept) for i in infos),
-                          "metric_rank_max": max(int(i.metric_rank) for i in infos)}
+                          "metric_rank_max": max(int(i.metric_rank) for i in infos),
+                          "gradient_ms_at_last_iterate": round(grad_at_iterate_ms, 2),
+                          "bicgstab_iters_at_last_iterate": int(sum(ginfo.iters_fwd) + sum(ginfo.iters_adj))}
         log(f"qn {name}: {iters} outer iterations, {np.mean(times) * 1e3:.1f} ms each")
     # the rank-S WPM alone (same shape, metric rank, weight and iterations)
     U = 0.1 * torch.randn((S, N, N, N), dtype=torch.float32, device=dev)
