@@ -5,6 +5,8 @@ bench.py runs.
   forward fields u_b and the adjoint fields w_b of the first and the last
   system against oracle solves, element by element (2e-4 relative; GPU tol
   1e-6, oracle tol 1e-13).
+* 128^3, complex64, the same launch set with the benchmark's 512 x 512 camera
+  1 um beyond the exit plane: camera images of the first and last systems.
 * 128^3, complex128, 4 illuminations: gradient and loss against the
   oracle's (1e-10; both sides tol 1e-13), the complex128 y pass at 128.
 * 96^3, complex64, the 96^3 workload's launch set of 8: forward and adjoint
@@ -144,6 +146,31 @@ def test_128_launch_set_of_16_fields_match_oracle(dev):
         ew = _rel(np.conj(w[b].cpu().numpy()), wr)
         assert eu < 2e-4 and ew < 2e-4, (b, eu, ew)
         print(f"128^3 launch set of 16, FP32, system {b}: field {eu:.2e}, adjoint field {ew:.2e}")
+
+
+def test_128_camera_images_of_the_launch_set_match_oracle(dev):
+    """The benchmark's camera section at full size: the 128^3 launch set of
+    16, the detector plane 1 um beyond the exit plane, a 512 x 512 camera of
+    pitch N h / 512 (FP32, tol 1e-6; the camera's complex products on the
+    matrix cores): the images of the first and the last system against the
+    oracle's camera sampling of its propagated fields (tol 1e-13)."""
+    from oracle import camera
+    x, y, idx = _c4_inputs()
+    N, B, M, d = C4.N, C4.B, 512, 1.0
+    pitch = N * C4.h_um / M
+    ctx = _ctx(C4, "f32", tol=1e-6, max_iter=300, det_dist_um=d, cam_n=M, cam_pitch_um=pitch)
+    img, info = ctx.forward(torch.from_numpy(x).to(dev, torch.float32), idx)
+    ctx.close()
+    assert tuple(img.shape) == (B, M, M)
+    m = _c4_model()
+    geom_d = lsmodel.Geometry(N=N, h=C4.h_um, lambda0=C4.lambda0_um, n_b=C4.n_b, det_dist=d)
+    for b in (0, B - 1):
+        ur, _, _ = _c4_oracle_system(b)
+        uin = lsmodel.incident_field(m.geom, syn.workload_directions(C4)[idx[b]])
+        ref = camera.sample(lsmodel.propagate((ur - uin)[-1], geom_d, d), N, C4.h_um, M, pitch)
+        err = _rel(img[b].cpu().numpy(), ref)
+        assert err < 2e-4, (b, err)
+        print(f"128^3 launch set of 16, 512^2 camera 1 um beyond the exit plane, FP32, system {b}: images {err:.2e}")
 
 
 def test_128_f64_gradient_matches_oracle(dev):
