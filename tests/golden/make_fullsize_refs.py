@@ -2,7 +2,7 @@
 tests that the oracle cannot finish inside a test (hours of FP64 CPU work
 otherwise repeated on every run).  Calls only oracle/ and synthetic/.
 
-    python tests/golden/make_fullsize_refs.py [grad|fields|strong|strong_fields|strong256_fields|prox|all] [workers]
+    python tests/golden/make_fullsize_refs.py [grad|fields|strong|strong_fields|strong256_fields|prox|prox_tau|all] [workers]
 
 grad: the 256^3 workload with contrast x1.5 (c5_ls256_f32), the first two
       illuminations of its mini-batch.  Measurements y = H(x_true) (oracle
@@ -31,6 +31,7 @@ prox: the weighted TV prox of the same workload: iso TV, nonnegativity,
       metric tau I + u u^T (rank one), lambda 1e-3, 200 dual iterations
       (Section 4.1 iteration, Theorem 3.1 projection), kept at 8192 seeded
       voxels together with whole-array sums.
+prox_tau: the same prox under the metric tau I (no u).
 Each file records a digest of the oracle sources it was made with and one
 of its input arrays; the tests refuse a file whose oracle digest no longer
 matches, or whose inputs differ from those the synthetic generators give.
@@ -236,6 +237,19 @@ def make_prox() -> None:
              inputs=array_digest(v, u))
 
 
+def make_prox_tau() -> None:
+    w = syn.WORKLOADS["c5_ls256_f32"]
+    v, tau, _ = syn.prox_inputs(w)
+    t0 = time.time()
+    x = tvprox.wprox(v, tau, None, w.prox_lambda, "iso", "nonneg", n_iter=w.prox_iters)
+    print(f"prox (metric tau I) {time.time() - t0:.0f} s", flush=True)
+    sel = sample_index(x.size, 7262)
+    np.savez(os.path.join(HERE, "c5_prox256_tau_k200.npz"), x_sel=x.ravel()[sel], sel=sel,
+             x_norm=np.linalg.norm(x), x_sum=x.sum(), x_pos=int(np.count_nonzero(x > 0)),
+             n_iter=w.prox_iters, lam=w.prox_lambda, tau=tau, digest=source_digest(PROX_SOURCES),
+             inputs=array_digest(v))
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     workers = int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1)
@@ -251,3 +265,5 @@ if __name__ == "__main__":
         make_strong256_fields(workers)
     if what in ("prox", "all"):
         make_prox()
+    if what in ("prox_tau", "all"):
+        make_prox_tau()

@@ -54,6 +54,7 @@ CASES = [
     ("c5_grad256_b2.npz", GRAD, lambda: _grad_inputs("c5_ls256_f32")),
     ("c5_fields256_b32.npz", GRAD, lambda: _field_inputs("c5_ls256_f32")),
     ("c5_prox256_k200.npz", PROX, lambda: _prox_inputs("c5_ls256_f32")),
+    ("c5_prox256_tau_k200.npz", PROX, lambda: _prox_inputs("c5_ls256_f32")[:1]),
     ("c6_grad128_strong_b2.npz", GRAD, lambda: _grad_inputs("c6_ls128_strong")),
     ("c6_fields128_strong_b15.npz", GRAD, lambda: _field_inputs("c6_ls128_strong")),
     ("c7_fields256_strong_b32.npz", GRAD, lambda: _field_inputs("c7_ls256_strong")),

@@ -25,7 +25,7 @@ bench.py runs.
   whole-array one) plus the whole-array norm (2e-4).
 * 256^3 weighted prox (iso TV, nonnegativity, metric tau I + u u^T, lambda
   1e-3) at its 200 dual iterations, FP32 (2e-4) and FP64 (1e-10), against
-  the oracle's stored samples and norm.
+  the oracle's stored samples and norm; the same under the metric tau I.
 
 The measurements of the 128^3 cases are stand-in detector images (the
 gradient is defined for any measurement); those of the 256^3 case are the
@@ -307,6 +307,27 @@ def test_256_prox_200_iterations_matches_stored_oracle(dev, prec):
     assert err < lim, err
     assert abs(float(torch.linalg.norm(x.double())) - float(ref["x_norm"])) < lim * float(ref["x_norm"])
     print(f"256^3 prox, 200 iterations, {prec}: sampled relative error {err:.2e}")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_256_prox_tau_metric_200_iterations_matches_stored_oracle(dev, prec):
+    """The benchmark's metric-tau-I prox (one fused kernel per dual
+    iteration) at 256^3 and its 200 dual iterations: FP32 (2e-4) and FP64
+    (1e-10) against the oracle's stored samples and norm."""
+    from paper_2307_02043_amd import WProx
+    v, tau, _ = syn.prox_inputs(C5)
+    ref = _golden("c5_prox256_tau_k200.npz", ("oracle/tvprox.py",), v)
+    assert int(ref["n_iter"]) == C5.prox_iters == 200
+    rd = torch.float32 if prec == "f32" else torch.float64
+    px = WProx(v.shape, prec)
+    x, info = px(torch.from_numpy(v).to(dev, rd), tau, None, C5.prox_lambda, "iso", "nonneg", C5.prox_iters)
+    px.close()
+    lim = 2e-4 if prec == "f32" else 1e-10
+    xs = x.reshape(-1)[torch.from_numpy(ref["sel"]).to(dev)].double().cpu().numpy()
+    err = _rel(xs, ref["x_sel"])
+    assert err < lim, err
+    assert abs(float(torch.linalg.norm(x.double())) - float(ref["x_norm"])) < lim * float(ref["x_norm"])
+    print(f"256^3 prox under tau I, 200 iterations, {prec}: sampled relative error {err:.2e}")
 
 
 C6 = syn.WORKLOADS["c6_ls128_strong"]
