@@ -2,7 +2,7 @@
 tests that the oracle cannot finish inside a test (hours of FP64 CPU work
 otherwise repeated on every run).  Calls only oracle/ and synthetic/.
 
-    python tests/golden/make_fullsize_refs.py [grad|fields|strong|strong_fields|strong256_fields|prox|prox_tau|all] [workers]
+    python tests/golden/make_fullsize_refs.py [grad|fields|strong|strong_fields|strong256_fields|prox|prox_tau|qn_step|all] [workers]
 
 grad: the 256^3 workload with contrast x1.5 (c5_ls256_f32), the first two
       illuminations of its mini-batch.  Measurements y = H(x_true) (oracle
@@ -32,6 +32,11 @@ prox: the weighted TV prox of the same workload: iso TV, nonnegativity,
       (Section 4.1 iteration, Theorem 3.1 projection), kept at 8192 seeded
       voxels together with whole-array sums.
 prox_tau: the same prox under the metric tau I (no u).
+qn_step: the first outer iteration (Algorithm 4.1, S = 4 subsets of 16) on the
+      128^3 workload from x_0 = 0.5 x_true (in float32 values) with stand-in
+      detector images for its first subset: the subset gradient (oracle
+      solves at tol 1e-13) and the iterate x_1, kept at 8192 seeded voxels
+      with their norms.
 Each file records a digest of the oracle sources it was made with and one
 of its input arrays; the tests refuse a file whose oracle digest no longer
 matches, or whose inputs differ from those the synthetic generators give.
@@ -50,7 +55,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import synthetic as syn  # noqa: E402
-from oracle import lsmodel, tvprox  # noqa: E402
+from oracle import bqnpm, lsmodel, tvprox  # noqa: E402
 
 SAMPLES = 8192
 
@@ -237,6 +242,44 @@ def make_prox() -> None:
              inputs=array_digest(v, u))
 
 
+QN_SOURCES = GRAD_SOURCES + PROX_SOURCES + ("oracle/bqnpm.py",)
+
+
+def qn_step_inputs():
+    """x_0, the first subset's stand-in detector images, directions and the
+    subsets of the full-size outer-iteration reference (the GPU test
+    rebuilds them the same way)."""
+    w = syn.WORKLOADS["c4_ls128_f32"]
+    x0 = (0.5 * syn.scattering_potential(syn.make_phantom(w))).astype(np.float32).astype(np.float64)
+    y0 = syn.detector_images(w.B, w.N, np.random.default_rng(w.seed("noise") + 200)).astype(np.complex64)
+    subsets = [list(range(s * w.B, (s + 1) * w.B)) for s in range(4)]
+    return x0, y0, syn.workload_directions(w), subsets
+
+
+def make_qn_step(workers: int) -> None:
+    w = syn.WORKLOADS["c4_ls128_f32"]
+    geom = lsmodel.Geometry(N=w.N, h=w.h_um, lambda0=w.lambda0_um, n_b=w.n_b)
+    t0 = time.time()
+    m = lsmodel.LSModel(geom, workers=workers)
+    x0, y0, dirs, subsets = qn_step_inputs()
+    S = len(subsets)
+    xt = syn.scattering_potential(syn.make_phantom(w))
+    g0, f0, st = m.grad(x0, y0.astype(np.complex128), dirs, subsets[0], S / w.L, 1e-13, 300)
+    print(f"gradient {time.time() - t0:.0f} s, iterations {st}", flush=True)
+    alpha = float(np.abs(g0).max() / xt.max())
+    prm = bqnpm.BQNPMParams(S=S, a=1.0 / 20, lam=1.0 / w.N ** 3, alpha=alpha, prox_iters=50)
+    # the first outer iteration takes subset 0, whose gradient is g0
+    it = bqnpm.BQNPM(prm, lambda s, x: g0)
+    x1, sp, _ = it.step(x0)
+    assert sp == 0
+    print(f"outer step {time.time() - t0:.0f} s", flush=True)
+    sel = sample_index(x0.size, 7263)
+    np.savez(os.path.join(HERE, "c4_qn_step128_b16.npz"), sel=sel, g_sel=g0.ravel()[sel],
+             g_norm=np.linalg.norm(g0), loss=f0, x1_sel=x1.ravel()[sel], x1_norm=np.linalg.norm(x1),
+             alpha=alpha, a=prm.a, lam=prm.lam, S=S, prox_iters=prm.prox_iters,
+             iters=np.array(st, np.int32), digest=source_digest(QN_SOURCES), inputs=array_digest(x0, y0, dirs))
+
+
 def make_prox_tau() -> None:
     w = syn.WORKLOADS["c5_ls256_f32"]
     v, tau, _ = syn.prox_inputs(w)
@@ -267,3 +310,5 @@ if __name__ == "__main__":
         make_prox()
     if what in ("prox_tau", "all"):
         make_prox_tau()
+    if what in ("qn_step", "all"):
+        make_qn_step(workers)

@@ -50,7 +50,15 @@ def _prox_inputs(name):
     return v, u
 
 
+def _qn_step_inputs():
+    w = syn.WORKLOADS["c4_ls128_f32"]
+    x0 = (0.5 * syn.scattering_potential(syn.make_phantom(w))).astype(np.float32).astype(np.float64)
+    y0 = syn.detector_images(w.B, w.N, np.random.default_rng(w.seed("noise") + 200)).astype(np.complex64)
+    return x0, y0, syn.workload_directions(w)
+
+
 CASES = [
+    ("c4_qn_step128_b16.npz", GRAD + PROX + ("oracle/bqnpm.py",), _qn_step_inputs),
     ("c5_grad256_b2.npz", GRAD, lambda: _grad_inputs("c5_ls256_f32")),
     ("c5_fields256_b32.npz", GRAD, lambda: _field_inputs("c5_ls256_f32")),
     ("c5_prox256_k200.npz", PROX, lambda: _prox_inputs("c5_ls256_f32")),

@@ -7,6 +7,8 @@ bench.py runs.
   1e-6, oracle tol 1e-13).
 * 128^3, complex64, the same launch set with the benchmark's 512 x 512 camera
   1 um beyond the exit plane: camera images of the first and last systems.
+* 128^3, the outer iteration's first step (S = 4 subsets of 16) in FP32 and
+  FP64: the subset gradient and x_1 against stored oracle results.
 * 128^3, complex128, 4 illuminations: gradient and loss against the
   oracle's (1e-10; both sides tol 1e-13), the complex128 y pass at 128.
 * 96^3, complex64, the 96^3 workload's launch set of 8: forward and adjoint
@@ -171,6 +173,50 @@ def test_128_camera_images_of_the_launch_set_match_oracle(dev):
         err = _rel(img[b].cpu().numpy(), ref)
         assert err < 2e-4, (b, err)
         print(f"128^3 launch set of 16, 512^2 camera 1 um beyond the exit plane, FP32, system {b}: images {err:.2e}")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_128_first_outer_iteration_matches_stored_oracle(dev, prec):
+    """The benchmark's outer iteration at full size (128^3, S = 4 subsets of
+    16, 50 dual iterations per WPM): the gradient of the first subset (the
+    benchmark's launch set of 16) and the first iterate x_1 from x_0 =
+    0.5 x_true, against the oracle's (solves at tol 1e-13) stored at 8192
+    voxels with their norms; FP32 at tol 1e-6 (2e-4), FP64 at tol 1e-13
+    (1e-10)."""
+    from paper_2307_02043_amd import QNIteration, WProx
+    N, B = C4.N, C4.B
+    x0 = (0.5 * syn.scattering_potential(syn.make_phantom(C4))).astype(np.float32).astype(np.float64)
+    y0 = syn.detector_images(B, N, np.random.default_rng(C4.seed("noise") + 200)).astype(np.complex64)
+    dirs = syn.workload_directions(C4)
+    ref = _golden("c4_qn_step128_b16.npz", ("oracle/green.py", "oracle/lsmodel.py", "oracle/tvprox.py",
+                                             "oracle/bqnpm.py"), x0, y0, dirs)
+    S = int(ref["S"])
+    subsets = [list(range(s * B, (s + 1) * B)) for s in range(S)]
+    rd, cd, tol, lim = ((torch.float32, torch.complex64, 1e-6, 2e-4) if prec == "f32"
+                        else (torch.float64, torch.complex128, 1e-13, 1e-10))
+    ls = _ctx(C4, prec, tol=tol, max_iter=300)
+    x = torch.from_numpy(x0).to(dev, rd)
+    y = torch.zeros((C4.L, N, N), dtype=cd, device=dev)
+    y[:B] = torch.from_numpy(y0).to(dev, cd)
+    sel = torch.from_numpy(ref["sel"]).to(dev)
+    g, f, info = ls.grad(x, y[:B].contiguous(), subsets[0], S / C4.L)
+    assert info.status == 0
+    eg = _rel(g.reshape(-1)[sel].double().cpu().numpy(), ref["g_sel"])
+    assert eg < lim, eg
+    assert abs(float(torch.linalg.norm(g.double())) - float(ref["g_norm"])) < lim * float(ref["g_norm"])
+    px = WProx((N, N, N), prec)
+    qn = QNIteration(ls, px, subsets, float(ref["a"]), float(ref["lam"]), float(ref["alpha"]), 0.8, 1e8,
+                     prox_iters=int(ref["prox_iters"]))
+    xk = x.clone()
+    inf = qn.step(xk, y)
+    qn.close()
+    px.close()
+    ls.close()
+    assert inf.k == 1 and inf.subset == 0
+    ex = _rel(xk.reshape(-1)[sel].double().cpu().numpy(), ref["x1_sel"])
+    assert ex < lim, ex
+    assert abs(float(torch.linalg.norm(xk.double())) - float(ref["x1_norm"])) < lim * float(ref["x1_norm"])
+    print(f"128^3 first outer iteration, {prec}: subset gradient {eg:.2e}, x_1 {ex:.2e} (8192 voxels)")
 
 
 def test_128_f64_gradient_matches_oracle(dev):
