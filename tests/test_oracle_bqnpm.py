@@ -148,3 +148,14 @@ def test_outer_iteration_rank_S_metric_when_tau_max_binds():
                                "iso", "nonneg", n_iter=200)
             np.testing.assert_allclose(x, ref, rtol=1e-12, atol=1e-13)
     assert np.all(x >= 0)
+
+
+def test_subset_choice_strategies():
+    """Section 4.3: the first S iterations visit the subsets in order; then
+    strategy I cycles through them and strategy II takes the given draw."""
+    prm = bqnpm.BQNPMParams(S=3, a=0.1, lam=1e-3, alpha=1.0)
+    it = bqnpm.BQNPM(prm, lambda s, x: x)
+    assert [it.pick(k) for k in range(1, 4)] == [0, 1, 2]
+    assert [it.pick(k, draw=2) for k in range(1, 4)] == [0, 1, 2]   # draws ignored for k <= S
+    assert [it.pick(k) for k in range(4, 10)] == [0, 1, 2, 0, 1, 2]
+    assert [it.pick(k, draw=d) for k, d in zip(range(4, 8), [2, 2, 0, 1])] == [2, 2, 0, 1]
