@@ -7,6 +7,10 @@
 // with the parity classes of ghat_P; the twiddles are scalars per line and
 // are applied inside the passes, so only N-point FFTs are ever run.
 //
+// Power-of-two grids run the register-resident line passes of green_reg.hip;
+// at N = 96 in complex64 the z and y passes are register passes as well
+// (padded 24 x 8 lines) between the LDS x passes here.
+//
 // Passes (one system per blockIdx.z, all systems of a batch in one launch):
 //   Zf  : z lines, prologue (x . v, x . u_in, S^T conj r, ...), both z parities
 //   Xf  : x rows, both x parities              (split path)
