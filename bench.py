@@ -448,6 +448,9 @@ def main():
                          f"{'complex64' if cw.precision == 'f32' else 'complex128'}, tol {cw.tol:g}, "
                          f"x = {cw.x_eval_scale:g} x_true")
         configs[name] = r
+    if "c3_ls96_f32" in configs:
+        # the 96^3 configuration names a persistent batched solver in a HIP graph
+        configs["c3_ls96_f32"]["graph_replay"] = bench_graph_replay(syn.WORKLOADS["c3_ls96_f32"], dev)
 
     # ---- propagated detector plane (angular spectrum), same workload ---------
     det = bench_detprop(w, dev, xt, dirs, idx, scale, args.steps, head["ms_per_step"]) \
@@ -574,6 +577,50 @@ def bench_detprop(w, dev, xt, dirs, idx, scale, steps, base_ms, d_um=1.0, cam_n=
         else:
             out["ms_per_step"] = round(ms, 3)
             log(f"detector plane {d_um} um beyond the exit plane: {ms:.2f} ms per gradient step")
+    return out
+
+
+def bench_graph_replay(w, dev, steps=20):
+    """The workload's batched gradient with the BiCGSTAB iteration replayed
+    as a captured HIP graph (BQ_FLAG_GRAPH) against the same context
+    launching its kernels one by one, both without per-pass events (a
+    timed pass turns replay off).  Same inputs as the configs section."""
+    import torch
+
+    import synthetic as syn
+    from paper_2307_02043_amd import LSContext
+
+    xt = syn.scattering_potential(syn.make_phantom(w))
+    dirs = syn.workload_directions(w)
+    idx = syn.batch_indices(w)
+    fwd = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, "f32", w.model, tol=1e-6, max_iter=w.max_iter)
+    yc, _ = fwd.forward(torch.from_numpy(xt).to(dev, torch.float32), idx)
+    fwd.close()
+    y = syn.add_noise(yc.cpu().numpy(), w.snr_db, np.random.default_rng(w.seed("noise")))
+    rd, cd = (torch.float32, torch.complex64) if w.precision == "f32" else (torch.float64, torch.complex128)
+    xe = torch.from_numpy(w.x_eval_scale * xt).to(dev, rd)
+    yt = torch.from_numpy(y).to(dev, cd)
+    out = {}
+    for key, graphs in (("eager_ms_per_step", False), ("graph_ms_per_step", True)):
+        ctx = LSContext(w.N, w.h_um, w.lambda0_um, w.n_b, dirs, w.precision, w.model, tol=w.tol,
+                        max_iter=w.max_iter, graphs=graphs)
+        ctx.autotune(w.B)
+        for _ in range(2):
+            g, loss, info = ctx.grad(xe, yt, idx, 1.0 / w.B)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            g, loss, info = ctx.grad(xe, yt, idx, 1.0 / w.B)
+        torch.cuda.synchronize()
+        out[key] = round((time.perf_counter() - t) / steps * 1e3, 3)
+        if graphs:
+            out["graph_captures"] = ctx.info()["graph_captures"]
+            out["same_loss_bits"] = bool(loss == out["loss"])
+        else:
+            out["loss"] = loss
+        ctx.close()
+    log(f"{w.name} graph replay: {out['graph_ms_per_step']:.3f} ms per step against "
+        f"{out['eager_ms_per_step']:.3f} ms launching each kernel")
     return out
 
 
