@@ -366,8 +366,26 @@ void launch_out(bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a
 // k_dual, operation for operation, so x does not depend on which thread
 // forms it.
 //
-// x at (z, y, x); the three components of R at that voxel are returned in
-// c[] (the caller reuses them for the dual step).
+// x at (z, y, x) from the six R values of its divergence (the backward
+// neighbour m and the voxel c of each component; a backward neighbour off
+// the low face is not used) and v there.
+template <typename T, bool NONNEG>
+__device__ inline T x_of(const ProxArgs<T>& p, T lt, int z, int y, int x, T zm, T zc, T ym, T yc, T xm, T xc,
+                         T vv) {
+  T d = 0;
+  d += z > 0 ? zm : T(0);
+  d -= z < p.nz - 1 ? zc : T(0);
+  d += y > 0 ? ym : T(0);
+  d -= y < p.ny - 1 ? yc : T(0);
+  d += x > 0 ? xm : T(0);
+  d -= x < p.nx - 1 ? xc : T(0);
+  T w = vv - lt * d;
+  if constexpr (NONNEG) w = w > T(0) ? w : T(0);
+  return w;
+}
+
+// x at (z, y, x), voxel j, with its loads; the three components of R at
+// that voxel are returned in c[] (the caller reuses them for the dual step).
 template <typename T, bool NONNEG>
 __device__ inline T x_tau(const ProxArgs<T>& p, const T* __restrict__ R, T lt, int z, int y, int x, size_t j,
                           T* c) {
@@ -379,23 +397,18 @@ __device__ inline T x_tau(const ProxArgs<T>& p, const T* __restrict__ R, T lt, i
   const T ym = Ry[y > 0 ? j - sy : j + sy], yc = Ry[j];
   const T xm = Rx[x > 0 ? j - 1 : j + 1], xc = Rx[j];
   c[0] = zc; c[1] = yc; c[2] = xc;
-  T d = 0;
-  d += z > 0 ? zm : T(0);
-  d -= z < p.nz - 1 ? zc : T(0);
-  d += y > 0 ? ym : T(0);
-  d -= y < p.ny - 1 ? yc : T(0);
-  d += x > 0 ? xm : T(0);
-  d -= x < p.nx - 1 ? xc : T(0);
-  T w = p.v[j] - lt * d;
-  if constexpr (NONNEG) w = w > T(0) ? w : T(0);
-  return w;
+  return x_of<T, NONNEG>(p, lt, z, y, x, zm, zc, ym, yc, xm, xc, p.v[j]);
 }
 
 // Each thread walks one (y, x) column through a chunk of zc planes, so x and
 // R at plane z + 1, formed for the z difference, are the next step's centre;
 // x at x + 1 is the next lane's centre (a cross-lane shift; the last lane of
-// a wave forms it itself).  Traversal "rows" are (chunk, y) pairs, so rows
-// y and y + 1 of one chunk are neighbours in the XCD row slabs.
+// a wave forms it itself).  Of the divergences of x at (z + 1, y) and at
+// (z, y + 1), three R values are already held: R_z and R_y at the voxel and
+// R_z at (z - 1, y + 1), loaded by the previous step.  On a high face the
+// forward neighbour's x is not used, and the voxel itself stands in for it
+// (in-bounds loads, no branch).  Traversal "rows" are (chunk, y) pairs, so
+// rows y and y + 1 of one chunk are neighbours in the XCD row slabs.
 //
 // par: slot of t_k in the state (t_{k+1} is written to the other slot by
 // one thread; no other thread reads that slot in this launch)
@@ -411,19 +424,28 @@ __global__ void __launch_bounds__(PX_WG) k_dual0(ProxArgs<T> p, const T* __restr
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
   const unsigned nchunk = (unsigned)((p.nz + zc - 1) / zc);
   const bool last_lane = (threadIdx.x & 63) == 63;
+  const T* Rz = Rin;
+  const T* Ry = Rin + V;
+  const T* Rx = Rin + 2 * V;
   for_rows<PX_WG>(p.nx, nchunk * (unsigned)p.ny, [&](unsigned row, int x) {
     const int ch = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)ch * (unsigned)p.ny);
     const int z0 = ch * zc, z1 = min(z0 + zc, p.nz);
     const bool hy = y < p.ny - 1, hx = x < p.nx - 1;
+    const size_t dy = hy ? sy : 0;  // offset of (z, y + 1) from the voxel
     size_t i = ((size_t)z0 * p.ny + y) * p.nx + x;
-    T rc[3], rn[3], ry[3], rx[3];
+    T rc[3], rx[3];
     T xc = x_tau<T, NONNEG>(p, Rin, lt, z0, y, x, i, rc);
+    // R_z at (z - 1, y + 1), not used at z = 0
+    T rzy = Rz[(z0 > 0 && hy) ? i + sy - sz : i];
     for (int z = z0; z < z1; ++z) {
-      // at the high faces the forward neighbour is replaced by the backward
-      // one (every dimension is >= 2) and its difference discarded below
       const bool hz = z < p.nz - 1;
-      const T xz = x_tau<T, NONNEG>(p, Rin, lt, hz ? z + 1 : z - 1, y, x, hz ? i + sz : i - sz, rn);
-      const T xy = x_tau<T, NONNEG>(p, Rin, lt, z, hy ? y + 1 : y - 1, x, hy ? i + sy : i - sy, ry);
+      const size_t j1 = hz ? i + sz : i;  // (z + 1, y)
+      const size_t j2 = i + dy;           // (z, y + 1)
+      const T z1c = Rz[j1], y1m = Ry[y > 0 ? j1 - sy : j1 + sy], y1c = Ry[j1];
+      const T x1m = Rx[x > 0 ? j1 - 1 : j1 + 1], x1c = Rx[j1], v1 = p.v[j1];
+      const T z2c = Rz[j2], y2c = Ry[j2], x2m = Rx[x > 0 ? j2 - 1 : j2 + 1], x2c = Rx[j2], v2 = p.v[j2];
+      const T xz = x_of<T, NONNEG>(p, lt, hz ? z + 1 : z, y, x, rc[0], z1c, y1m, y1c, x1m, x1c, v1);
+      const T xy = x_of<T, NONNEG>(p, lt, z, hy ? y + 1 : y, x, rzy, z2c, rc[1], y2c, x2m, x2c, v2);
       T xx = __shfl_down(xc, 1, 64);
       if (last_lane && hx) xx = x_tau<T, NONNEG>(p, Rin, lt, z, y, x + 1, i + 1, rx);
       const T gz = hz ? xz - xc : T(0);
@@ -449,7 +471,8 @@ __global__ void __launch_bounds__(PX_WG) k_dual0(ProxArgs<T> p, const T* __restr
       nt_st(&Rout[V + i], qy + mom * (qy - oy));
       nt_st(&Rout[2 * V + i], qx + mom * (qx - ox));
       xc = xz;
-      rc[0] = rn[0]; rc[1] = rn[1]; rc[2] = rn[2];
+      rc[0] = z1c; rc[1] = y1c; rc[2] = x1c;
+      rzy = z2c;
       i += sz;
     }
   });
