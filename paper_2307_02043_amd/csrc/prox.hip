@@ -433,10 +433,13 @@ __global__ void __launch_bounds__(PX_WG) k_dual0(ProxArgs<T> p, const T* __restr
     const bool hy = y < p.ny - 1, hx = x < p.nx - 1;
     const size_t dy = hy ? sy : 0;  // offset of (z, y + 1) from the voxel
     size_t i = ((size_t)z0 * p.ny + y) * p.nx + x;
-    T rc[3], rx[3];
+    T rc[3];
     T xc = x_tau<T, NONNEG>(p, Rin, lt, z0, y, x, i, rc);
-    // R_z at (z - 1, y + 1), not used at z = 0
+    // R_z at (z - 1, y + 1) and, for the last lane, at (z - 1, y, x + 1);
+    // not used at z = 0
     T rzy = Rz[(z0 > 0 && hy) ? i + sy - sz : i];
+    T rzx = T(0);
+    if (last_lane && hx) rzx = Rz[z0 > 0 ? i + 1 - sz : i + 1];
     for (int z = z0; z < z1; ++z) {
       const bool hz = z < p.nz - 1;
       const size_t j1 = hz ? i + sz : i;  // (z + 1, y)
@@ -447,7 +450,12 @@ __global__ void __launch_bounds__(PX_WG) k_dual0(ProxArgs<T> p, const T* __restr
       const T xz = x_of<T, NONNEG>(p, lt, hz ? z + 1 : z, y, x, rc[0], z1c, y1m, y1c, x1m, x1c, v1);
       const T xy = x_of<T, NONNEG>(p, lt, z, hy ? y + 1 : y, x, rzy, z2c, rc[1], y2c, x2m, x2c, v2);
       T xx = __shfl_down(xc, 1, 64);
-      if (last_lane && hx) xx = x_tau<T, NONNEG>(p, Rin, lt, z, y, x + 1, i + 1, rx);
+      if (last_lane && hx) {  // x at (z, y, x + 1): R_x at the voxel is its backward neighbour
+        const size_t j3 = i + 1;
+        const T z3c = Rz[j3], y3m = Ry[y > 0 ? j3 - sy : j3 + sy], y3c = Ry[j3], x3c = Rx[j3], v3 = p.v[j3];
+        xx = x_of<T, NONNEG>(p, lt, z, y, x + 1, rzx, z3c, y3m, y3c, rc[2], x3c, v3);
+        rzx = z3c;
+      }
       const T gz = hz ? xz - xc : T(0);
       const T gy = hy ? xy - xc : T(0);
       const T gx = hx ? xx - xc : T(0);
