@@ -293,46 +293,58 @@ __global__ void __launch_bounds__(PX_WG) k_unorm(ProxArgs<T> p) {
 // P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1}).
 // R and P are read and written once per voxel (non-temporal); a and u are
 // re-read as stencil neighbours and keep the default cache policy.
+// Each thread walks one (y, x) column through a chunk of zc planes: x at
+// plane z + 1, formed for the z difference, is the next step's centre, and
+// x at x + 1 is the next lane's centre (a cross-lane shift; the last lane
+// of a wave forms it itself).  On a high face the voxel itself stands in
+// for the forward neighbour, whose difference is discarded (in-bounds
+// loads, no branch).  Traversal rows are (chunk, y) pairs.
 template <typename T, bool HAS_U, bool NONNEG>
-__global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p) {
+__global__ void __launch_bounds__(PX_WG) k_dual(ProxArgs<T> p, int zc) {
   const ProxState* stp = p.st;
   const T theta = (T)stp->theta;
   const T sig = (T)p.sigma, mom = (T)stp->mom;
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
-  const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
-  for_rows<PX_WG>(p.nx, nrows, [&](unsigned row, int x) {
-    const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
-    const size_t base = (size_t)row * p.nx;
-    const size_t i = base + x;
-    // at the high faces the forward neighbour is replaced by the backward one
-    // (every dimension is >= 2) and discarded by the select below: all loads
-    // are issued together, none sits behind a branch
-    const T xc = xval<T, HAS_U, NONNEG>(p, i, theta);
-    const T xz = xval<T, HAS_U, NONNEG>(p, z < p.nz - 1 ? i + sz : i - sz, theta);
-    const T xy = xval<T, HAS_U, NONNEG>(p, y < p.ny - 1 ? i + sy : i - sy, theta);
-    const T xx = xval<T, HAS_U, NONNEG>(p, x < p.nx - 1 ? i + 1 : i - 1, theta);
-    const T gz = z < p.nz - 1 ? xz - xc : T(0);
-    const T gy = y < p.ny - 1 ? xy - xc : T(0);
-    const T gx = x < p.nx - 1 ? xx - xc : T(0);
-    T qz = nt_ld(&p.R[i]) + sig * gz;
-    T qy = nt_ld(&p.R[V + i]) + sig * gy;
-    T qx = nt_ld(&p.R[2 * V + i]) + sig * gx;
-    if (p.iso) {
-      const T n = sqrt(qz * qz + qy * qy + qx * qx);
-      if (n > T(1)) {
-        const T inv = T(1) / n;
-        qz *= inv; qy *= inv; qx *= inv;
+  const unsigned nchunk = (unsigned)((p.nz + zc - 1) / zc);
+  const bool last_lane = (threadIdx.x & 63) == 63;
+  for_rows<PX_WG>(p.nx, nchunk * (unsigned)p.ny, [&](unsigned row, int x) {
+    const int ch = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)ch * (unsigned)p.ny);
+    const int z0 = ch * zc, z1 = min(z0 + zc, p.nz);
+    const bool hy = y < p.ny - 1, hx = x < p.nx - 1;
+    const size_t dy = hy ? sy : 0;  // offset of (z, y + 1) from the voxel
+    size_t i = ((size_t)z0 * p.ny + y) * p.nx + x;
+    T xc = xval<T, HAS_U, NONNEG>(p, i, theta);
+    for (int z = z0; z < z1; ++z) {
+      const bool hz = z < p.nz - 1;
+      const T xz = xval<T, HAS_U, NONNEG>(p, hz ? i + sz : i, theta);
+      const T xy = xval<T, HAS_U, NONNEG>(p, i + dy, theta);
+      T xx = __shfl_down(xc, 1, 64);
+      if (last_lane && hx) xx = xval<T, HAS_U, NONNEG>(p, i + 1, theta);
+      const T gz = hz ? xz - xc : T(0);
+      const T gy = hy ? xy - xc : T(0);
+      const T gx = hx ? xx - xc : T(0);
+      T qz = nt_ld(&p.R[i]) + sig * gz;
+      T qy = nt_ld(&p.R[V + i]) + sig * gy;
+      T qx = nt_ld(&p.R[2 * V + i]) + sig * gx;
+      if (p.iso) {
+        const T n = sqrt(qz * qz + qy * qy + qx * qx);
+        if (n > T(1)) {
+          const T inv = T(1) / n;
+          qz *= inv; qy *= inv; qx *= inv;
+        }
+      } else {
+        qz = fmin(fmax(qz, T(-1)), T(1));
+        qy = fmin(fmax(qy, T(-1)), T(1));
+        qx = fmin(fmax(qx, T(-1)), T(1));
       }
-    } else {
-      qz = fmin(fmax(qz, T(-1)), T(1));
-      qy = fmin(fmax(qy, T(-1)), T(1));
-      qx = fmin(fmax(qx, T(-1)), T(1));
+      const T oz = nt_ld(&p.P[i]), oy = nt_ld(&p.P[V + i]), ox = nt_ld(&p.P[2 * V + i]);
+      nt_st(&p.P[i], qz); nt_st(&p.P[V + i], qy); nt_st(&p.P[2 * V + i], qx);
+      nt_st(&p.R[i], qz + mom * (qz - oz));
+      nt_st(&p.R[V + i], qy + mom * (qy - oy));
+      nt_st(&p.R[2 * V + i], qx + mom * (qx - ox));
+      xc = xz;
+      i += sz;
     }
-    const T oz = nt_ld(&p.P[i]), oy = nt_ld(&p.P[V + i]), ox = nt_ld(&p.P[2 * V + i]);
-    nt_st(&p.P[i], qz); nt_st(&p.P[V + i], qy); nt_st(&p.P[2 * V + i], qx);
-    nt_st(&p.R[i], qz + mom * (qz - oz));
-    nt_st(&p.R[V + i], qy + mom * (qy - oy));
-    nt_st(&p.R[2 * V + i], qx + mom * (qx - ox));
   });
 }
 
@@ -346,9 +358,9 @@ __global__ void __launch_bounds__(PX_WG) k_out(ProxArgs<T> p) {
 // launch k_dual / k_out of the rank-one path, specialised on the constraint
 // (without u the metric-tau-I path below runs instead)
 template <typename T>
-void launch_dual(bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
-  if (nonneg) hipLaunchKernelGGL((k_dual<T, true, true>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_dual<T, true, false>), g, b, 0, s, a);
+void launch_dual(bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a, int zc) {
+  if (nonneg) hipLaunchKernelGGL((k_dual<T, true, true>), g, b, 0, s, a, zc);
+  else hipLaunchKernelGGL((k_dual<T, true, false>), g, b, 0, s, a, zc);
 }
 template <typename T>
 void launch_out(bool nonneg, dim3 g, dim3 b, hipStream_t s, const ProxArgs<T>& a) {
@@ -537,6 +549,24 @@ int px_grid(size_t V) {
   return (int)g;
 }
 
+// z chunk per thread of the column-walking dual kernels (k_dual, k_dual0)
+// and their grid: about 2^18 columns-times-chunks in flight (8 planes at
+// 128^3, 32 at 256^3: the best of 2..32 measured), at least 2; the grid
+// covers the (chunk, y) rows, a multiple of the XCD count.
+struct ZWalk {
+  int zc;
+  dim3 grid;
+};
+ZWalk zwalk_shape(const bq_prox* p) {
+  int zc = 2;
+  while (zc < 32 && (size_t)zc * 2 * 262144 <= p->V) zc *= 2;
+  const size_t rows = (size_t)((p->nz + zc - 1) / zc) * p->ny;
+  const size_t rps = p->nx >= PX_WG ? 1 : (size_t)(PX_WG / p->nx);
+  size_t g0 = std::min<size_t>((rows + rps - 1) / rps, 2048);
+  if (g0 >= NUM_XCD) g0 = (g0 + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+  return {zc, dim3((unsigned)g0)};
+}
+
 // One run of the rank-one iteration (u not null) with `slots` root passes
 // launched per dual iteration; the final device state goes to *hs.
 template <typename T>
@@ -584,9 +614,10 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
     }
   };
   // one dual iteration captured as a graph and replayed n_iter times
+  const ZWalk zw = zwalk_shape(p);
   if (!replay_iterations(p, n_iter, [&](hipStream_t) {
         primal();
-        launch_dual<T>(nonneg, g, b, s, a);
+        launch_dual<T>(nonneg, zw.grid, b, s, a, zw.zc);
       })) {
     p->err = "graph capture or launch of the dual iteration failed";
     return BQ_EDEVICE;
@@ -644,15 +675,9 @@ bq_status run_wprox_tau(bq_prox* p, const void* v, double tau, double lam, int t
     p->err = "copy of the starting dual point failed";
     return BQ_EDEVICE;
   }
-  // z chunk per thread: about 2^18 columns-times-chunks in flight (8 planes
-  // at 128^3, 32 at 256^3), at least 2; the grid covers the (chunk, y) rows
-  int zc = 2;
-  while (zc < 32 && (size_t)zc * 2 * 262144 <= V) zc *= 2;
-  const size_t rows = (size_t)((p->nz + zc - 1) / zc) * p->ny;
-  const size_t rps = p->nx >= PX_WG ? 1 : (size_t)(PX_WG / p->nx);
-  size_t g0 = std::min<size_t>((rows + rps - 1) / rps, 2048);
-  if (g0 >= NUM_XCD) g0 = (g0 + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
-  const dim3 gd((unsigned)g0);
+  const ZWalk zw = zwalk_shape(p);
+  const dim3 gd = zw.grid;
+  const int zc = zw.zc;
   auto dual = [&](const T* rin, T* rout, int par) {
     if (nonneg) hipLaunchKernelGGL((k_dual0<T, true>), gd, b, 0, s, a, rin, rout, par, zc);
     else hipLaunchKernelGGL((k_dual0<T, false>), gd, b, 0, s, a, rin, rout, par, zc);
