@@ -437,7 +437,7 @@ def main():
         cpu = cpu_baseline(w, xt, dirs, idx, iters / (args.steps * B), args.cpu_iters, args.cpu_iters_1t)
 
     # ---- the other workloads ------------------------------------------------
-    configs = {}
+    per_workload = {}
     for name in [c for c in args.configs.split(",") if c]:
         cw = syn.WORKLOADS[name]
         steps = 3 if cw.N >= 256 else 5 if cw.N >= 128 else 20
@@ -447,10 +447,10 @@ def main():
                          f"mini-batch gradient, {cw.N}^3, batch {cw.B} of {cw.L}, "
                          f"{'complex64' if cw.precision == 'f32' else 'complex128'}, tol {cw.tol:g}, "
                          f"x = {cw.x_eval_scale:g} x_true")
-        configs[name] = r
-    if "c3_ls96_f32" in configs:
+        per_workload[name] = r
+    if "c3_ls96_f32" in per_workload:
         # the 96^3 configuration names a persistent batched solver in a HIP graph
-        configs["c3_ls96_f32"]["graph_replay"] = bench_graph_replay(syn.WORKLOADS["c3_ls96_f32"], dev)
+        per_workload["c3_ls96_f32"]["graph_replay"] = bench_graph_replay(syn.WORKLOADS["c3_ls96_f32"], dev)
 
     # ---- propagated detector plane (angular spectrum), same workload ---------
     det = bench_detprop(w, dev, xt, dirs, idx, scale, args.steps, head["ms_per_step"]) \
@@ -494,7 +494,7 @@ def main():
         "solver": head["solver"],
         "passes_ms_per_step": head["passes_ms_per_step"],
         "autotune": head["autotune"],
-        "configs": configs,
+        "configs": per_workload,
         "prox": prox,
         "prox_latency": prox_small,
         "qn": qn,
