@@ -373,10 +373,9 @@ bq_status bq_wprox(bq_prox* p, const void* v, double tau, const void* U, int r, 
  *                          default stream); the call synchronises it
  *   other arguments        as bq_wprox (the same computation and result)
  * Scratch needed, in bytes rounded up to 256 each: the image, the dual
- * momentum (3 images), the dual point unless P_io is given (3 images), x at
- * rank >= 2 (1 image), a second momentum at rank 0 (3 images), plus about
- * 1 MB of partial sums and state: in FP32 every rank fits at 128^3, in FP64
- * at 96^3.
+ * momentum (3 images), the dual point unless P_io is given (3 images), a
+ * second momentum at rank 0 (3 images), plus about 1 MB of partial sums and
+ * state: in FP32 every rank fits at 128^3, in FP64 at 96^3.
  * Every call on a GPU uses that GPU's one array, which keeps the last
  * call's contents (each call initialises what it reads): calls that
  * overlap on one GPU (concurrent host threads, or streams whose work

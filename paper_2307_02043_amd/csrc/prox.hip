@@ -549,24 +549,6 @@ int px_grid(size_t V) {
   return (int)g;
 }
 
-// z chunk per thread of the column-walking dual kernels (k_dual, k_dual0)
-// and their grid: about 2^18 columns-times-chunks in flight (8 planes at
-// 128^3, 32 at 256^3: the best of 2..32 measured), at least 2; the grid
-// covers the (chunk, y) rows, a multiple of the XCD count.
-struct ZWalk {
-  int zc;
-  dim3 grid;
-};
-ZWalk zwalk_shape(const bq_prox* p) {
-  int zc = 2;
-  while (zc < 32 && (size_t)zc * 2 * 262144 <= p->V) zc *= 2;
-  const size_t rows = (size_t)((p->nz + zc - 1) / zc) * p->ny;
-  const size_t rps = p->nx >= PX_WG ? 1 : (size_t)(PX_WG / p->nx);
-  size_t g0 = std::min<size_t>((rows + rps - 1) / rps, 2048);
-  if (g0 >= NUM_XCD) g0 = (g0 + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
-  return {zc, dim3((unsigned)g0)};
-}
-
 // One run of the rank-one iteration (u not null) with `slots` root passes
 // launched per dual iteration; the final device state goes to *hs.
 template <typename T>
@@ -614,7 +596,7 @@ bq_status run_wprox_once(bq_prox* p, const void* v, double tau, const void* u, d
     }
   };
   // one dual iteration captured as a graph and replayed n_iter times
-  const ZWalk zw = zwalk_shape(p);
+  const ZWalk zw = zwalk_shape(p, PX_WG);
   if (!replay_iterations(p, n_iter, [&](hipStream_t) {
         primal();
         launch_dual<T>(nonneg, zw.grid, b, s, a, zw.zc);
@@ -675,7 +657,7 @@ bq_status run_wprox_tau(bq_prox* p, const void* v, double tau, double lam, int t
     p->err = "copy of the starting dual point failed";
     return BQ_EDEVICE;
   }
-  const ZWalk zw = zwalk_shape(p);
+  const ZWalk zw = zwalk_shape(p, PX_WG);
   const dim3 gd = zw.grid;
   const int zc = zw.zc;
   auto dual = [&](const T* rin, T* rout, int par) {
@@ -744,7 +726,7 @@ bq_status run_wprox(bq_prox* p, const void* v, double tau, const void* u, double
 
 void free_prox(bq_prox* p) {
   if (!p) return;
-  void* ptrs[] = {p->a, p->P, p->R, p->R2, p->xbuf, p->partial, p->st, p->rst, p->Pbak};
+  void* ptrs[] = {p->a, p->P, p->R, p->R2, p->partial, p->st, p->rst, p->Pbak};
   for (void* q : ptrs) if (q) (void)hipFree(q);
   if (p->ev) (void)hipEventDestroy(p->ev);
   if (p->own) (void)hipStreamDestroy(p->own);
@@ -804,7 +786,6 @@ bq_status bq_prox_create(int nz, int ny, int nx, int precision, void* stream, bq
   const size_t es = precision == BQ_F32 ? 4 : 8;
   if (hipMalloc(&p->a, p->V * es) != hipSuccess || hipMalloc(&p->P, 3 * p->V * es) != hipSuccess ||
       hipMalloc(&p->R, 3 * p->V * es) != hipSuccess ||
-      hipMalloc(&p->xbuf, p->V * es) != hipSuccess ||
       hipMalloc((void**)&p->partial, (size_t)p->np * PX_PART * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&p->st, sizeof(ProxState)) != hipSuccess ||
       hipMalloc((void**)&p->rst, prox_rank_state_bytes()) != hipSuccess) {
@@ -864,9 +845,9 @@ bq_status bq_wprox_noalloc(int nz, int ny, int nx, int precision, const void* v,
   if (r < 0 || r > BQ_PROX_MAX_RANK) return fail(BQ_EINVAL, "metric rank r must be in [0, BQ_PROX_MAX_RANK]");
   if (r > 0 && !U) return fail(BQ_EINVAL, "U is NULL with r > 0");
   // the workspace of a bq_prox object, laid out in the scratch array: the
-  // image a, the dual point P (unless the caller's), the momentum R, x(R)
-  // at rank >= 2, the second momentum buffer of the metric tau I, the
-  // partial sums and the two device states
+  // image a, the dual point P (unless the caller's), the momentum R, the
+  // second momentum buffer of the metric tau I, the partial sums and the
+  // two device states
   const size_t V = (size_t)nz * ny * nx;
   const size_t es = precision == BQ_F32 ? 4 : 8;
   const int np = px_grid(V);
@@ -875,7 +856,6 @@ bq_status bq_wprox_noalloc(int nz, int ny, int nx, int precision, const void* v,
   const size_t o_a = take(V * es);
   const size_t o_P = P_io ? 0 : take(3 * V * es);
   const size_t o_R = take(3 * V * es);
-  const size_t o_x = r >= 2 ? take(V * es) : 0;
   const size_t o_R2 = r == 0 ? take(3 * V * es) : 0;
   const size_t o_part = take((size_t)np * PX_PART * sizeof(double));
   const size_t o_st = take(sizeof(ProxState));
@@ -898,7 +878,6 @@ bq_status bq_wprox_noalloc(int nz, int ny, int nx, int precision, const void* v,
   p.a = base + o_a;
   p.P = P_io ? nullptr : base + o_P;
   p.R = base + o_R;
-  p.xbuf = r >= 2 ? base + o_x : nullptr;
   p.R2 = r == 0 ? base + o_R2 : nullptr;
   p.partial = (double*)(base + o_part);
   p.st = (ProxState*)(base + o_st);

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/bq.h"
+#include "bq_common.h"
 
 namespace bq {
 struct ProxState;
@@ -23,7 +24,6 @@ struct bq_prox {
   void* a = nullptr;
   void* P = nullptr;
   void* R = nullptr;
-  void* xbuf = nullptr;          // x(R) for metrics of rank >= 2
   double* partial = nullptr;     // np x PX_PART doubles
   void* Pbak = nullptr;          // copy of a caller's starting dual point (3V), for a rerun
   void* R2 = nullptr;            // second momentum buffer (3V) of the metric-tau-I path, on first use
@@ -76,6 +76,25 @@ bq_status run_with_pass_budget(bq_prox* p, void* P_io, size_t bytes3, bool root,
   }
   if (st == BQ_OK && root) slots_pref = std::max(2, std::min(full, seen));
   return st;
+}
+
+// z chunk per thread of the column-walking dual kernels (workgroups of wg
+// threads walking (y, x) columns through zc planes) and their grid: about
+// 2^18 columns-times-chunks in flight (8 planes at 128^3, 32 at 256^3: the
+// best of 2..32 measured), at least 2; the grid covers the (chunk, y) rows,
+// a multiple of the XCD count.
+struct ZWalk {
+  int zc;
+  dim3 grid;
+};
+inline ZWalk zwalk_shape(const bq_prox* p, int wg) {
+  int zc = 2;
+  while (zc < 32 && (size_t)zc * 2 * 262144 <= p->V) zc *= 2;
+  const size_t rows = (size_t)((p->nz + zc - 1) / zc) * p->ny;
+  const size_t rps = p->nx >= wg ? 1 : (size_t)(wg / p->nx);
+  size_t g0 = std::min<size_t>((rows + rps - 1) / rps, 2048);
+  if (g0 >= NUM_XCD) g0 = (g0 + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+  return {zc, dim3((unsigned)g0)};
 }
 
 // Runs body(stream) `count` times on p->own: one capture replayed as a graph,

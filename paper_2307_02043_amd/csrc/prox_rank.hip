@@ -23,8 +23,9 @@
 // point is the root of that point's piece.
 //
 // Kernels: k_div_r (a; FP64 partials of U^T d, U^T a and, at the warm-start
-// theta, S_A, T_A, Q_A), k_ssn_r (S_A, T_A, Q_A at a trial theta), k_xr
-// (x into a buffer), k_dual_x (P = Proj(R + sigma D x), momentum).
+// theta, S_A, T_A, Q_A), k_ssn_r (S_A, T_A, Q_A at a trial theta), k_dual_r
+// (x from a and U where the stencil needs it, P = Proj(R + sigma D x),
+// momentum) and, for the output, k_xr (x).
 // One-workgroup kernels reduce the partials in a fixed order and run the
 // small dense algebra (Cholesky, r <= 8) on the device.
 #include <cmath>
@@ -70,7 +71,6 @@ struct PRArgs {
   const T* v;
   const T* U;  // r x V
   T* a;
-  T* xbuf;
   T* P;
   T* R;
   double* partial;
@@ -409,60 +409,82 @@ __global__ void __launch_bounds__(256) k_pr_after_ssn(ProxRankState* st, const d
   }
 }
 
-// x = max(a - U theta, 0) (or a - U theta without the constraint)
+// x = max(a - U theta, 0) (or a - U theta without the constraint) at voxel i
+template <typename T, int R>
+__device__ inline T xr_at(const PRArgs<T>& p, size_t i, const T* th, bool nonneg) {
+  T z = p.a[i];
+#pragma unroll
+  for (int c = 0; c < R; ++c) z -= p.U[c * p.V + i] * th[c];
+  return nonneg ? (z > T(0) ? z : T(0)) : z;
+}
+
+// x into out (the output of a call)
 template <typename T, int R>
 __global__ void __launch_bounds__(PR_WG) k_xr(PRArgs<T> p, T* out) {
   T th[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) th[c] = (T)p.st->theta[c];
   const bool nonneg = p.st->nonneg;
-  for (size_t i = blockIdx.x * (size_t)PR_WG + threadIdx.x; i < p.V; i += (size_t)gridDim.x * PR_WG) {
-    T z = p.a[i];
-#pragma unroll
-    for (int c = 0; c < R; ++c) z -= p.U[c * p.V + i] * th[c];
-    out[i] = nonneg ? (z > T(0) ? z : T(0)) : z;
-  }
+  for (size_t i = blockIdx.x * (size_t)PR_WG + threadIdx.x; i < p.V; i += (size_t)gridDim.x * PR_WG)
+    out[i] = xr_at<T, R>(p, i, th, nonneg);
 }
 
-// P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1}).
-// R and P are streamed (non-temporal); x is re-read by the stencil.
-template <typename T>
-__global__ void __launch_bounds__(PR_WG) k_dual_x(PRArgs<T> p) {
+// P_k = Proj(R_k + sigma D x_k); R_{k+1} = P_k + mom (P_k - P_{k-1}), with x
+// formed from a and U where the stencil needs it (as k_xr forms it, so the
+// iterates do not depend on which thread forms it).  Each thread walks one
+// (y, x) column through a chunk of zc planes: x at plane z + 1 is the next
+// step's centre and x at x + 1 the next lane's (a cross-lane shift; the last
+// lane of a wave forms it itself).  On a high face the voxel itself stands
+// in for the forward neighbour, whose difference is discarded.  R and P are
+// streamed (non-temporal).
+template <typename T, int R>
+__global__ void __launch_bounds__(PR_WG) k_dual_r(PRArgs<T> p, int zc) {
+  T th[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) th[c] = (T)p.st->theta[c];
+  const bool nonneg = p.st->nonneg;
   const T sig = (T)p.sigma, mom = (T)p.st->mom;
   const size_t V = p.V, sz = (size_t)p.ny * p.nx, sy = (size_t)p.nx;
-  const T* xb = p.xbuf;
-  const unsigned nrows = (unsigned)p.nz * (unsigned)p.ny;
-  for_rows<PR_WG>(p.nx, nrows, [&](unsigned row, int x) {
-    const int z = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)z * (unsigned)p.ny);
-    const size_t base = (size_t)row * p.nx;
-    const size_t i = base + x;
-    // all loads issued (at the high faces the forward neighbour is replaced by
-    // the backward one, every dimension being >= 2), boundaries as selects
-    const T xc = xb[i];
-    const T xz = xb[z < p.nz - 1 ? i + sz : i - sz], xy = xb[y < p.ny - 1 ? i + sy : i - sy];
-    const T xx = xb[x < p.nx - 1 ? i + 1 : i - 1];
-    const T gz = z < p.nz - 1 ? xz - xc : T(0);
-    const T gy = y < p.ny - 1 ? xy - xc : T(0);
-    const T gx = x < p.nx - 1 ? xx - xc : T(0);
-    T qz = nt_ld(&p.R[i]) + sig * gz;
-    T qy = nt_ld(&p.R[V + i]) + sig * gy;
-    T qx = nt_ld(&p.R[2 * V + i]) + sig * gx;
-    if (p.iso) {
-      const T n = sqrt(qz * qz + qy * qy + qx * qx);
-      if (n > T(1)) {
-        const T inv = T(1) / n;
-        qz *= inv; qy *= inv; qx *= inv;
+  const unsigned nchunk = (unsigned)((p.nz + zc - 1) / zc);
+  const bool last_lane = (threadIdx.x & 63) == 63;
+  for_rows<PR_WG>(p.nx, nchunk * (unsigned)p.ny, [&](unsigned row, int x) {
+    const int ch = (int)(row / (unsigned)p.ny), y = (int)(row - (unsigned)ch * (unsigned)p.ny);
+    const int z0 = ch * zc, z1 = min(z0 + zc, p.nz);
+    const bool hy = y < p.ny - 1, hx = x < p.nx - 1;
+    const size_t dy = hy ? sy : 0;  // offset of (z, y + 1) from the voxel
+    size_t i = ((size_t)z0 * p.ny + y) * p.nx + x;
+    T xc = xr_at<T, R>(p, i, th, nonneg);
+    for (int z = z0; z < z1; ++z) {
+      const bool hz = z < p.nz - 1;
+      const T xz = xr_at<T, R>(p, hz ? i + sz : i, th, nonneg);
+      const T xy = xr_at<T, R>(p, i + dy, th, nonneg);
+      T xx = __shfl_down(xc, 1, 64);
+      if (last_lane && hx) xx = xr_at<T, R>(p, i + 1, th, nonneg);
+      const T gz = hz ? xz - xc : T(0);
+      const T gy = hy ? xy - xc : T(0);
+      const T gx = hx ? xx - xc : T(0);
+      T qz = nt_ld(&p.R[i]) + sig * gz;
+      T qy = nt_ld(&p.R[V + i]) + sig * gy;
+      T qx = nt_ld(&p.R[2 * V + i]) + sig * gx;
+      if (p.iso) {
+        const T n = sqrt(qz * qz + qy * qy + qx * qx);
+        if (n > T(1)) {
+          const T inv = T(1) / n;
+          qz *= inv; qy *= inv; qx *= inv;
+        }
+      } else {
+        qz = fmin(fmax(qz, T(-1)), T(1));
+        qy = fmin(fmax(qy, T(-1)), T(1));
+        qx = fmin(fmax(qx, T(-1)), T(1));
       }
-    } else {
-      qz = fmin(fmax(qz, T(-1)), T(1));
-      qy = fmin(fmax(qy, T(-1)), T(1));
-      qx = fmin(fmax(qx, T(-1)), T(1));
+      const T oz = nt_ld(&p.P[i]), oy = nt_ld(&p.P[V + i]), ox = nt_ld(&p.P[2 * V + i]);
+      nt_st(&p.P[i], qz); nt_st(&p.P[V + i], qy); nt_st(&p.P[2 * V + i], qx);
+      nt_st(&p.R[i], qz + mom * (qz - oz));
+      nt_st(&p.R[V + i], qy + mom * (qy - oy));
+      nt_st(&p.R[2 * V + i], qx + mom * (qx - ox));
+      xc = xz;
+      i += sz;
     }
-    const T oz = nt_ld(&p.P[i]), oy = nt_ld(&p.P[V + i]), ox = nt_ld(&p.P[2 * V + i]);
-    nt_st(&p.P[i], qz); nt_st(&p.P[V + i], qy); nt_st(&p.P[2 * V + i], qx);
-    nt_st(&p.R[i], qz + mom * (qz - oz));
-    nt_st(&p.R[V + i], qy + mom * (qy - oy));
-    nt_st(&p.R[2 * V + i], qx + mom * (qx - ox));
   });
 }
 
@@ -514,7 +536,6 @@ static bq_status run_rank_once(bq_prox* p, const void* v, double tau, const void
   a.v = (const T*)v;
   a.U = (const T*)U;
   a.a = (T*)p->a;
-  a.xbuf = (T*)p->xbuf;
   a.P = P_io ? (T*)P_io : (T*)p->P;
   a.R = (T*)p->R;
   a.partial = p->partial;
@@ -533,7 +554,8 @@ static bq_status run_rank_once(bq_prox* p, const void* v, double tau, const void
   }
   const int mp = p->max_passes_rank;
   const int n_ssn = nonneg ? slots : 0;
-  auto primal = [&](T* xdst) {
+  // divergence and root finding for the current momentum R
+  auto primal = [&]() {
     hipLaunchKernelGGL((k_div_r<T, R>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_pr_after_div<R>), dim3(1), dim3(256), 0, s, p->rst, (const double*)p->partial, np, mp);
     for (int j = 0; j < n_ssn; ++j) {
@@ -541,11 +563,11 @@ static bq_status run_rank_once(bq_prox* p, const void* v, double tau, const void
       hipLaunchKernelGGL((k_pr_after_ssn<R>), dim3(1), dim3(256), 0, s, p->rst, (const double*)p->partial, np,
                          mp, j == n_ssn - 1 ? 1 : 0);
     }
-    hipLaunchKernelGGL((k_xr<T, R>), g, b, 0, s, a, xdst);
   };
+  const ZWalk zw = zwalk_shape(p, PR_WG);
   if (!replay_iterations(p, n_iter, [&](hipStream_t) {
-        primal(a.xbuf);
-        hipLaunchKernelGGL((k_dual_x<T>), g, b, 0, s, a);
+        primal();
+        hipLaunchKernelGGL((k_dual_r<T, R>), zw.grid, b, 0, s, a, zw.zc);
       })) {
     p->err = "graph capture or launch of the dual iteration failed";
     return BQ_EDEVICE;
@@ -554,7 +576,8 @@ static bq_status run_rank_once(bq_prox* p, const void* v, double tau, const void
     p->err = "copy failed";
     return BQ_EDEVICE;
   }
-  primal((T*)x_out);
+  primal();
+  hipLaunchKernelGGL((k_xr<T, R>), g, b, 0, s, a, (T*)x_out);
   if (hipGetLastError() != hipSuccess) {
     p->err = "kernel launch failed";
     return BQ_EDEVICE;
