@@ -287,6 +287,21 @@ def test_wprox_row_lengths(dev, shape, r, tv):
     assert _rel(got, ref) < 1e-10, _rel(got, ref)
 
 
+@pytest.mark.parametrize("shape", [(101, 96, 130), (37, 97, 300)])
+@pytest.mark.parametrize("r", [0, 1, 3])
+def test_wprox_column_walk_ragged_chunks(dev, shape, r):
+    """The dual kernels of every rank walk x columns through chunks of z
+    planes (4 planes per thread at these sizes): a last chunk of one plane,
+    rows shorter than a workgroup (130) and longer than one (300), FP64
+    against the oracle."""
+    rng = np.random.default_rng(200 + r + shape[2])
+    v = 0.02 * rng.random(shape) + 0.005 * rng.standard_normal(shape)
+    U = None if r == 0 else 0.1 * rng.standard_normal(((r,) if r > 1 else ()) + shape)
+    ref = tp.wprox(v, 0.8, U, 2e-3, "iso", "nonneg", n_iter=12)
+    got, _, _ = _run(dev, shape, "f64", v, 0.8, U, 2e-3, "iso", "nonneg", 12)
+    assert _rel(got, ref) < 1e-10, _rel(got, ref)
+
+
 # ---- metric tau I (no u): one fused kernel per dual iteration ---------------
 
 @pytest.mark.parametrize("n_iter", [0, 1, 2, 7, 20])
