@@ -9,6 +9,9 @@ bench.py runs.
   1 um beyond the exit plane: camera images of the first and last systems.
 * 128^3, the outer iteration's first step (S = 4 subsets of 16) in FP32 and
   FP64: the subset gradient and x_1 against stored oracle results.
+* 128^3, the outer iteration's rank-4 WPM (tau 1, lambda 1/N^3, 50 dual
+  iterations) in FP32 and FP64 on seeded inputs: the image and its
+  correction x - max(v, 0) against the live oracle.
 * 128^3, complex128, 4 illuminations: gradient and loss against the
   oracle's (1e-10; both sides tol 1e-13), the complex128 y pass at 128.
 * 96^3, complex64, the 96^3 workload's launch set of 8: forward and adjoint
@@ -217,6 +220,45 @@ def test_128_first_outer_iteration_matches_stored_oracle(dev, prec):
     assert ex < lim, ex
     assert abs(float(torch.linalg.norm(xk.double())) - float(ref["x1_norm"])) < lim * float(ref["x1_norm"])
     print(f"128^3 first outer iteration, {prec}: subset gradient {eg:.2e}, x_1 {ex:.2e} (8192 voxels)")
+
+
+@functools.lru_cache(maxsize=None)
+def _c4_rank4_prox():
+    """The outer-iteration section's rank-S WPM at 128^3 (S = 4 columns of
+    U, tau 1, lambda 1/N^3, iso TV, nonnegativity, 50 dual iterations) on
+    seeded inputs: v and U as the smaller prox tests draw them (no exact
+    zeros in v: on an image with exact zeros, such as a phantom's
+    background, the oracle's test for the exact root, a full Newton step
+    that keeps its active set, can fail to hold in rounding at a root among
+    many kinks); inputs and the oracle's result."""
+    from oracle import tvprox as tp
+    shape = (C4.N,) * 3
+    rng = np.random.default_rng(C4.seed("prox") + 404)
+    v = (0.02 * rng.random(shape) + 0.005 * rng.standard_normal(shape)).astype(np.float32).astype(np.float64)
+    U = (0.1 * rng.standard_normal((4,) + shape)).astype(np.float32).astype(np.float64)
+    lam = 1.0 / C4.N ** 3
+    return v, U, lam, tp.wprox(v, 1.0, U, lam, "iso", "nonneg", n_iter=50)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_128_rank4_prox_50_iterations_matches_oracle(dev, prec):
+    """The rank-4 WPM the benchmark times next to the outer iteration, at its
+    size, rank, weight and iteration count.  With lambda = 1/N^3 the result
+    stays close to max(v, 0), so the correction x - max(v, 0) (the TV and
+    rank-4 terms) is compared as well."""
+    from paper_2307_02043_amd import WProx
+    v, U, lam, ref = _c4_rank4_prox()
+    rd = torch.float32 if prec == "f32" else torch.float64
+    px = WProx(v.shape, prec)
+    x, info = px(torch.from_numpy(v).to(dev, rd), 1.0, torch.from_numpy(U).to(dev, rd), lam, "iso", "nonneg", 50)
+    got = x.cpu().numpy().astype(np.float64)
+    px.close()
+    base = np.maximum(v, 0.0)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    err_corr = float(np.linalg.norm((got - base) - (ref - base)) / np.linalg.norm(ref - base))
+    print(f"128^3 rank-4 prox, 50 iterations, {prec}: x {err:.2e}, correction {err_corr:.2e}")
+    assert err < (2e-4 if prec == "f32" else 1e-10), err
+    assert err_corr < (2e-3 if prec == "f32" else 1e-8), err_corr
 
 
 def test_128_f64_gradient_matches_oracle(dev):
