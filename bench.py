@@ -694,7 +694,7 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):
     px(x, 1.0, U, lam, "iso", "nonneg", 50)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    px(x, 1.0, U, lam, "iso", "nonneg", 50)
+    _, pinfo = px(x, 1.0, U, lam, "iso", "nonneg", 50)
     torch.cuda.synchronize()
     prox_ms = (time.perf_counter() - t) * 1e3
     px.close()
@@ -705,7 +705,9 @@ def bench_qn(w, dev, xt, dirs, iters, grad_ms, S=4, plan=None):
             "iterations": iters,
             "variants": variants,
             "gradient_ms_same_batch": round(grad_ms, 2),
-            "rank_S_wprox_ms": round(prox_ms, 2)}
+            "rank_S_wprox_ms": round(prox_ms, 2),
+            "rank_S_wprox_root_evaluations_max": int(pinfo.newton_max),
+            "rank_S_wprox_status": int(pinfo.status)}
 
 
 def bench_prox(w, dev, reps=2):

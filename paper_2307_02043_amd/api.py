@@ -239,6 +239,9 @@ class ProxInfo:
     newton_max: int
     beta_last: float
     phi_last: float
+    # BQ_OK, or BQ_NOTCONV when the root of some dual iteration was not
+    # pinned down within the pass limit (the image is still returned)
+    status: int = 0
 
 
 class WProx:
@@ -299,7 +302,7 @@ class WProx:
                                int(n_iter), _ptr(x), _ptr(P), ct.byref(st))
         if s < 0:
             raise BQError(s, self._lib.bq_prox_last_error(self._h).decode())
-        return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last)
+        return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last, int(s))
 
 
 def wprox_noalloc(v: torch.Tensor, tau: float, u: torch.Tensor | None, lam: float, tv: str = "iso",
@@ -337,7 +340,7 @@ def wprox_noalloc(v: torch.Tensor, tau: float, u: torch.Tensor | None, lam: floa
                              _ptr(P), ct.byref(st), _stream_handle(stream))
     if s < 0:
         raise BQError(s, lib.bq_prox_last_error(None).decode())
-    return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last), s
+    return x, ProxInfo(st.newton_total, st.newton_max, st.beta_last, st.phi_last, int(s)), s
 
 
 @dataclass

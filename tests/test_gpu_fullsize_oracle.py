@@ -253,6 +253,7 @@ def test_128_rank4_prox_50_iterations_matches_oracle(dev, prec):
     x, info = px(torch.from_numpy(v).to(dev, rd), 1.0, torch.from_numpy(U).to(dev, rd), lam, "iso", "nonneg", 50)
     got = x.cpu().numpy().astype(np.float64)
     px.close()
+    assert info.status == 0, "a dual iteration's root was not pinned down"
     base = np.maximum(v, 0.0)
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     err_corr = float(np.linalg.norm((got - base) - (ref - base)) / np.linalg.norm(ref - base))

@@ -315,7 +315,7 @@ def test_wprox_tau_metric_iteration_counts_and_rows(dev, n_iter, shape, tv, cset
     ref = tp.wprox(v, 0.9, None, 2e-3, tv, cset, n_iter=n_iter)
     got, info, _ = _run(dev, shape, "f64", v, 0.9, None, 2e-3, tv, cset, n_iter)
     assert _rel(got, ref) < 1e-10, _rel(got, ref)
-    assert info.newton_total == 0 and info.newton_max == 0
+    assert info.newton_total == 0 and info.newton_max == 0 and info.status == 0
     if cset == "nonneg":
         assert np.all(got >= 0)
 
